@@ -38,8 +38,12 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 extern "C" {
 
@@ -556,10 +560,119 @@ void step(const Model& m, const S* f, S* fout, S T, S g, Work<S>& w) {
     }
 }
 
+
+// ---------------------------------------------------------------- adjoint
+// Reverse mode of one step (Eqs. 1, 2, 3, 7-10, 20-22), obtained by the chain
+// rule written out by hand.  With the equilibrium in momentum form
+//   A_i(rho, m) = w_i [rho + 3 e_i.m + (4.5 (e_i.m)^2 - 1.5 |m|^2) / rho]
+// (A_i(rho, rho u) = f^eq_i(rho, u)), the collision of Eqs. 1 and 10 reads
+//   f*_i = (1 - 1/tau) f_i + (1/tau - 1) A_i(rho, j) + A_i(rho, j + F),
+// and the step is f_{t+1,i}(x + e_i) = f*_i(x).  Given lam = dJ/df_{t+1}:
+//   mu_i(x) = lam_i(x + e_i)                                  (streaming)
+//   rho_bar, j_bar, F_bar from the partial derivatives of A    (collision)
+//   U_bar from F_bar through the force (D^T = -D: A is symmetric and B
+//        antisymmetric, both circulant, so A^-1 B is antisymmetric)
+//   dJ/df_k(x) = (1 - 1/tau) mu_k + rho_bar + e_k.j_bar + U_bar dU/drho,
+// and the parameter gradients dJ/dg = sum U_bar dU/dg, dJ/dT = sum U_bar dU/dT.
+// dU/drho, dU/dg and dU/dT come from the dual-number evaluation of U.
+void dA_drho_dm(int i, double rho, double mx, double my, double* drho, double* dmx, double* dmy) {
+    double em = EX[i] * mx + EY[i] * my;
+    double m2 = mx * mx + my * my;
+    *drho = WQ[i] * (1.0 - (4.5 * em * em - 1.5 * m2) / (rho * rho));
+    *dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 3.0 * mx) / rho);
+    *dmy = WQ[i] * (3.0 * EY[i] + (9.0 * em * EY[i] - 3.0 * my) / rho);
+}
+
+void adjoint_step(const Model& m, const double* f, const double* lam_next, double* lam, double* grad) {
+    const int nx = m.p.nx, ny = m.p.ny;
+    const size_t N = (size_t)nx * ny;
+    Work<double> w;
+    forces<double>(m, f, m.p.T, m.p.g, w);
+    std::vector<double> Fbx(N), Fby(N), rbar(N), jbx(N), jby(N);
+    const double tau = m.p.tau;
+    // collision and streaming
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t c = (size_t)y * nx + x;
+            double mu[9];
+            for (int i = 0; i < 9; ++i) {
+                int xd = (x + EX[i] + nx) % nx, yd = (y + EY[i] + ny) % ny;
+                mu[i] = lam_next[i * N + (size_t)yd * nx + xd];
+            }
+            double rho = w.rho[c], jx = w.jx[c], jy = w.jy[c];
+            double mx = jx + w.Fx[c], my = jy + w.Fy[c];
+            double rb = 0, jbx_ = 0, jby_ = 0, fbx = 0, fby = 0;
+            for (int i = 0; i < 9; ++i) {
+                double a_r, a_x, a_y, b_r, b_x, b_y;
+                dA_drho_dm(i, rho, jx, jy, &a_r, &a_x, &a_y);
+                dA_drho_dm(i, rho, mx, my, &b_r, &b_x, &b_y);
+                rb += mu[i] * ((1.0 / tau - 1.0) * a_r + b_r);
+                jbx_ += mu[i] * ((1.0 / tau - 1.0) * a_x + b_x);
+                jby_ += mu[i] * ((1.0 / tau - 1.0) * a_y + b_y);
+                fbx += mu[i] * b_x;
+                fby += mu[i] * b_y;
+            }
+            for (int k = 0; k < 9; ++k) lam[k * N + c] = (1.0 - 1.0 / tau) * mu[k] + rb + EX[k] * jbx_ + EY[k] * jby_;
+            rbar[c] = rb; jbx[c] = jbx_; jby[c] = jby_;
+            Fbx[c] = fbx; Fby[c] = fby;
+        }
+    }
+    // force -> U_bar
+    std::vector<double> Ubar(N, 0.0), ax(N), ay(N), dax(N), day(N);
+    const bool sc = (m.p.force == 0 || m.p.force == 2), zc = (m.p.force == 1 || m.p.force == 2);
+    const double wsc = (m.p.force == 2) ? (1.0 - 2.0 * m.p.A) : 1.0;
+    const double wzc = (m.p.force == 2) ? m.p.A : 1.0;
+    if (sc) {
+        // F = -2 s Phi (D_x Phi, D_y Phi):  Phi_bar = -2 s (F_bar . D Phi) + D^T(-2 s Phi F_bar)
+        for (size_t c = 0; c < N; ++c) {
+            double s = (w.U[c] >= 0.0) ? 1.0 : -1.0;
+            ax[c] = -2.0 * s * w.phi[c] * wsc * Fbx[c];
+            ay[c] = -2.0 * s * w.phi[c] * wsc * Fby[c];
+        }
+        for (int y = 0; y < ny; ++y) derivative_line<double>(m.p.grad, nx, &ax[(size_t)y * nx], 1, &dax[(size_t)y * nx], 1);
+        for (int x = 0; x < nx; ++x) derivative_line<double>(m.p.grad, ny, &ay[x], nx, &day[x], nx);
+        for (size_t c = 0; c < N; ++c) {
+            double s = (w.U[c] >= 0.0) ? 1.0 : -1.0;
+            double phibar = -2.0 * s * wsc * (Fbx[c] * w.gx[c] + Fby[c] * w.gy[c]) - dax[c] - day[c];
+            // Phi = sqrt|U|: dPhi/dU = s / (2 Phi)
+            Ubar[c] += phibar * s / (2.0 * w.phi[c]);
+        }
+    }
+    if (zc) {
+        // F = -(D_x U, D_y U):  U_bar = -D^T F_bar = D_x F_bar_x + D_y F_bar_y
+        for (size_t c = 0; c < N; ++c) { ax[c] = wzc * Fbx[c]; ay[c] = wzc * Fby[c]; }
+        for (int y = 0; y < ny; ++y) derivative_line<double>(m.p.grad, nx, &ax[(size_t)y * nx], 1, &dax[(size_t)y * nx], 1);
+        for (int x = 0; x < nx; ++x) derivative_line<double>(m.p.grad, ny, &ay[x], nx, &day[x], nx);
+        for (size_t c = 0; c < N; ++c) Ubar[c] += dax[c] + day[c];
+    }
+    // U = g (k p(rho, T) - rho/3): chain into rho and the parameters
+    double gg = 0.0, gT = 0.0;
+    for (size_t c = 0; c < N; ++c) {
+        Dual dr = potential_U<Dual>(m, Dual(w.rho[c], 1.0), Dual(m.p.T, 0.0), Dual(m.p.g, 0.0));
+        Dual dT = potential_U<Dual>(m, Dual(w.rho[c], 0.0), Dual(m.p.T, 1.0), Dual(m.p.g, 0.0));
+        Dual dg = potential_U<Dual>(m, Dual(w.rho[c], 0.0), Dual(m.p.T, 0.0), Dual(m.p.g, 1.0));
+        double rnl = Ubar[c] * dr.d;
+        for (int k = 0; k < 9; ++k) lam[k * N + c] += rnl;
+        gg += Ubar[c] * dg.d;
+        gT += Ubar[c] * dT.d;
+    }
+    grad[0] += gg;
+    grad[1] += gT;
+}
+
 }  // namespace
 
 // ================================================================ C API
 extern "C" {
+
+// Number of OpenMP threads the parallel loops use (1 without OpenMP).
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int orc_critical(const orc_params* p, double* Tc, double* rhoc) {
     CritResult c = critical_point(*p);
@@ -655,6 +768,76 @@ int orc_tangent_run(const orc_params* p, int64_t nsteps, double* f, double* df, 
         a.swap(b);
     }
     for (size_t i = 0; i < 9 * N; ++i) { f[i] = a[i].v; df[i] = a[i].d; }
+    return 0;
+}
+
+
+// Reverse mode of one step: lam = (d f_{t+1} / d f_t)^T lam_next for the state f
+// (= f_t), and grad[0] += dJ/dg, grad[1] += dJ/dT.  Layouts [9][ny][nx].
+int orc_adjoint_step(const orc_params* p, const double* f, const double* lam_next, double* lam, double* grad) {
+    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5)) return 1;
+    Model m = make_model(*p);
+    adjoint_step(m, f, lam_next, lam, grad);
+    return 0;
+}
+
+// Gradient of J = sum_x (rho_n(x) - target(x))^2 after nsteps steps from the
+// initial state f0 = f^eq(rho0, u0): dJ/df0 (layout [9][ny][nx]), dJ/drho0
+// (holding u0 fixed: f^eq is linear in rho), dJ/dg and dJ/dT.  States are kept
+// every `every` steps and each segment is recomputed before its reverse sweep.
+int orc_adjoint_run(const orc_params* p, int64_t nsteps, int64_t every, const double* rho0, const double* ux0,
+                    const double* uy0, const double* target, double* J, double* dJ_df0, double* dJ_drho0,
+                    double* grad) {
+    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5) || every < 1) return 1;
+    Model m = make_model(*p);
+    const size_t N = (size_t)p->nx * p->ny;
+    std::vector<double> f0(9 * N);
+    orc_init(p, rho0, ux0, uy0, f0.data());
+    const int64_t nseg = (nsteps + every - 1) / every;
+    std::vector<std::vector<double>> ck(nseg > 0 ? nseg : 1);
+    Work<double> w;
+    std::vector<double> cur(f0), nxt(9 * N);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (s % every == 0) ck[s / every] = cur;
+        step<double>(m, cur.data(), nxt.data(), p->T, p->g, w);
+        cur.swap(nxt);
+    }
+    // objective and its cotangent at step n
+    std::vector<double> lam(9 * N), lam2(9 * N);
+    double Jv = 0.0;
+    for (size_t c = 0; c < N; ++c) {
+        double r = cur[0 * N + c];
+        for (int i = 1; i < 9; ++i) r += cur[i * N + c];
+        double d = r - target[c];
+        Jv += d * d;
+        for (int i = 0; i < 9; ++i) lam[i * N + c] = 2.0 * d;
+    }
+    grad[0] = 0.0;
+    grad[1] = 0.0;
+    std::vector<std::vector<double>> seg;
+    for (int64_t sidx = nseg - 1; sidx >= 0; --sidx) {
+        int64_t t0 = sidx * every, t1 = std::min(nsteps, t0 + every);
+        seg.assign((size_t)(t1 - t0), std::vector<double>());
+        std::vector<double> a = ck[sidx];
+        for (int64_t t = t0; t < t1; ++t) {
+            seg[(size_t)(t - t0)] = a;
+            step<double>(m, a.data(), nxt.data(), p->T, p->g, w);
+            a.swap(nxt);
+        }
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            adjoint_step(m, seg[(size_t)(t - t0)].data(), lam.data(), lam2.data(), grad);
+            lam.swap(lam2);
+        }
+    }
+    *J = Jv;
+    if (dJ_df0) std::memcpy(dJ_df0, lam.data(), sizeof(double) * 9 * N);
+    if (dJ_drho0) {
+        for (size_t c = 0; c < N; ++c) {
+            double acc = 0.0;
+            for (int i = 0; i < 9; ++i) acc += lam[i * N + c] * f0[i * N + c] / rho0[c];
+            dJ_drho0[c] = acc;
+        }
+    }
     return 0;
 }
 

@@ -66,7 +66,11 @@ def load(path: str):
     L.orc_run.argtypes = [P, C.c_int64, _D]
     L.orc_moments.argtypes = [P, _D, _D, _D, _D, _D, _D, _D]
     L.orc_tangent_run.argtypes = [P, C.c_int64, _D, _D, C.c_double, C.c_double]
-    for fn in ("orc_critical", "orc_maxwell", "orc_run", "orc_tangent_run"):
+    L.orc_threads.argtypes = []
+    L.orc_adjoint_step.argtypes = [P, _D, _D, _D, _D]
+    L.orc_adjoint_run.argtypes = [P, C.c_int64, C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]
+    for fn in ("orc_critical", "orc_maxwell", "orc_run", "orc_tangent_run", "orc_threads", "orc_adjoint_step",
+               "orc_adjoint_run"):
         getattr(L, fn).restype = C.c_int
     return L
 
@@ -94,6 +98,11 @@ def _ptr(a):
         return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_D)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def critical(p: Params):
@@ -177,3 +186,31 @@ def tangent_run(p: Params, f, df, nsteps: int, dT: float = 0.0, dg: float = 0.0)
     if lib().orc_tangent_run(C.byref(p.c()), int(nsteps), _ptr(f), _ptr(df), dT, dg):
         raise ValueError("invalid parameters")
     return f, df
+
+
+def adjoint_step(p: Params, f, lam_next):
+    """Reverse mode of one step at state f: returns (dJ/df_t, [dJ/dg, dJ/dT])."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lam_next = np.ascontiguousarray(lam_next, dtype=np.float64)
+    lam = np.empty_like(f)
+    grad = np.zeros(2)
+    if lib().orc_adjoint_step(C.byref(p.c()), _ptr(f), _ptr(lam_next), _ptr(lam), _ptr(grad)):
+        raise ValueError("invalid parameters")
+    return lam, grad
+
+
+def adjoint_run(p: Params, rho0, target, nsteps: int, every: int = 70, ux0=None, uy0=None):
+    """J = sum (rho_n - target)^2 after nsteps from f^eq(rho0, u0) and its gradients:
+    returns dict(J, df0, drho0, dg, dT)."""
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    ux0 = None if ux0 is None else np.ascontiguousarray(ux0, dtype=np.float64)
+    uy0 = None if uy0 is None else np.ascontiguousarray(uy0, dtype=np.float64)
+    J = C.c_double()
+    df0 = np.empty((9, p.ny, p.nx))
+    drho0 = np.empty((p.ny, p.nx))
+    grad = np.zeros(2)
+    if lib().orc_adjoint_run(C.byref(p.c()), int(nsteps), int(every), _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(target),
+                             C.byref(J), _ptr(df0), _ptr(drho0), _ptr(grad)):
+        raise ValueError("invalid parameters")
+    return {"J": J.value, "df0": df0, "drho0": drho0, "dg": grad[0], "dT": grad[1]}

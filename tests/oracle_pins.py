@@ -468,6 +468,82 @@ def pin_tangent_matches_differences():
     assert np.max(np.abs(fd - jvp)) < 1e-6 * np.max(np.abs(jvp)), np.max(np.abs(fd - jvp))
 
 
+# ------------------------------------------------------------------ adjoint
+def _adjoint_case(eos="cs", force="sc", grad="hdm", nx=14, ny=11, tr=0.7, seed=3, tau=0.8):
+    p = eos_params(eos)
+    p.nx, p.ny, p.force, p.grad, p.tau = nx, ny, force, grad, tau
+    p.A = 0.3 if force == "hybrid" else 0.0
+    tc, _ = O.critical(p)
+    p.T = tr * tc
+    rv, rl, _ = O.maxwell(p, p.T)
+    rho0 = I.droplet(nx, ny, rv, rl, min(nx, ny) / 3.5, 3.0, cx=nx * 0.4, cy=ny * 0.6, noise=1e-2 * rv, seed=seed)
+    ux0 = I.uniform_noise((ny, nx), 1e-3, seed + 1)
+    f = O.run(p, O.init(p, rho0, ux0, None), 3)
+    return p, f, rho0, rv, rl
+
+
+def pin_adjoint_dot_product():
+    """<lam, T df> = <A^T lam, df> + dJ/dT dT + dJ/dg dg for one step, where T is
+    the forward-mode (dual-number) tangent and A^T the hand-written adjoint:
+    the two are derived independently, so agreement to rounding pins both."""
+    rng = np.random.default_rng(21)
+    for eos, force, grad in (("cs", "sc", "hdm"), ("vdw", "zc", "hdm"), ("pr", "sc", "hdm"), ("rks", "hybrid", "hdm"),
+                             ("rk", "zc", "cdm"), ("vdw", "sc", "cdm")):
+        p, f, _, _, _ = _adjoint_case(eos, force, grad)
+        lam = rng.standard_normal(f.shape)
+        df = rng.standard_normal(f.shape) * 1e-2 * f
+        dT, dg = 0.3 * p.T, 0.7
+        _, jvp = O.tangent_run(p, f, df, 1, dT=dT, dg=dg)
+        lam0, grad_ = O.adjoint_step(p, f, lam)
+        lhs = float(np.sum(lam * jvp))
+        rhs = float(np.sum(lam0 * df)) + grad_[0] * dg + grad_[1] * dT
+        scale = float(np.sum(np.abs(lam * jvp)))
+        assert abs(lhs - rhs) < 1e-12 * scale, (eos, force, grad, lhs, rhs)
+
+
+def pin_adjoint_finite_differences():
+    """Gradients of J = sum (rho_n - target)^2 after n steps with respect to g, T
+    and rho0 (along a random direction) against central differences."""
+    p, _, rho0, rv, rl = _adjoint_case("cs", "sc", "hdm", nx=16, ny=12)
+    n = 25
+    pt = eos_params("cs")
+    pt.nx, pt.ny, pt.T, pt.g, pt.tau = p.nx, p.ny, p.T, 1.02, p.tau
+    target = O.moments(pt, O.run(pt, O.init(pt, rho0), n))["rho"]
+    res = O.adjoint_run(p, rho0, target, n, every=7)
+
+    def J(T=p.T, g=p.g, r0=rho0):
+        q = eos_params("cs")
+        q.nx, q.ny, q.T, q.g, q.tau = p.nx, p.ny, T, g, p.tau
+        rho = O.moments(q, O.run(q, O.init(q, r0), n))["rho"]
+        return float(np.sum((rho - target) ** 2))
+
+    hg = 1e-6 * p.g
+    fd_g = (J(g=p.g + hg) - J(g=p.g - hg)) / (2 * hg)
+    hT = 1e-6 * p.T
+    fd_T = (J(T=p.T + hT) - J(T=p.T - hT)) / (2 * hT)
+    dirn = I.uniform_noise(rho0.shape, 1.0, 99) * rv
+    hr = 1e-6
+    fd_r = (J(r0=rho0 + hr * dirn) - J(r0=rho0 - hr * dirn)) / (2 * hr)
+    ad_r = float(np.sum(res["drho0"] * dirn))
+    assert abs(res["J"] - J()) < 1e-14 * max(1e-30, abs(res["J"])) + 1e-300
+    assert abs(res["dg"] / fd_g - 1) < 1e-5, (res["dg"], fd_g)
+    assert abs(res["dT"] / fd_T - 1) < 1e-5, (res["dT"], fd_T)
+    assert abs(ad_r / fd_r - 1) < 1e-5, (ad_r, fd_r)
+
+
+def pin_adjoint_checkpoint_invariance():
+    """The checkpoint interval changes only what is recomputed: the gradient is
+    bitwise the same for every interval."""
+    p, _, rho0, _, _ = _adjoint_case("vdw", "zc", "hdm", nx=12, ny=10)
+    target = rho0 * 1.01
+    a = O.adjoint_run(p, rho0, target, 12, every=1)
+    b = O.adjoint_run(p, rho0, target, 12, every=5)
+    c = O.adjoint_run(p, rho0, target, 12, every=12)
+    for k in ("df0", "drho0"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+    assert a["dg"] == b["dg"] == c["dg"] and a["dT"] == b["dT"] == c["dT"]
+
+
 # ------------------------------------------------------------------ Sec. 5.3, Table 1
 def laplace_sigma(tr, R=32, n=128, steps=8000):
     """Surface tension from Laplace's law on one droplet: sigma = (p_in - p_out) R_e,
@@ -499,6 +575,7 @@ FAST = [
     pin_pr_alpha_at_tc, pin_acentric_factor, pin_maxwell_vdw_table, pin_maxwell_near_critical, pin_equilibrium_moments,
     pin_edm_collision, pin_streaming_shift, pin_mass_momentum_conservation, pin_uniform_fixed_point,
     pin_x_invariance, pin_shift_equivariance, pin_mirror_symmetry, pin_shear_wave_viscosity,
-    pin_flat_interface_equilibrium, pin_tangent_matches_differences,
+    pin_flat_interface_equilibrium, pin_tangent_matches_differences, pin_adjoint_dot_product,
+    pin_adjoint_finite_differences, pin_adjoint_checkpoint_invariance,
 ]
 SLOW = [pin_maxwell_equal_area, pin_hdm_beats_cdm_coexistence, pin_table1_laplace]

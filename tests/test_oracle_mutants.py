@@ -55,6 +55,17 @@ MUTANTS = {
     "velocity_output_full_force": ("if (vx) vx[c] = (w.jx[c] + 0.5 * w.Fx[c]) / w.rho[c];", "if (vx) vx[c] = (w.jx[c] + w.Fx[c]) / w.rho[c];"),
     "pressure_output_sign": ("if (pr) pr[c] = w.rho[c] / 3.0 + w.U[c];", "if (pr) pr[c] = w.rho[c] / 3.0 - w.U[c];"),
     "dual_division_rule": ("return Dual(q, (x.d - q * y.d) / y.v);", "return Dual(q, (x.d + q * y.d) / y.v);"),
+    "adjoint_stream_direction": ("mu[i] = lam_next[i * N + (size_t)yd * nx + xd];",
+                                 "mu[i] = lam_next[i * N + (size_t)((y - EY[i] + ny) % ny) * nx + (x - EX[i] + nx) % nx];"),
+    "adjoint_relaxation_factor": ("rb += mu[i] * ((1.0 / tau - 1.0) * a_r + b_r);", "rb += mu[i] * ((1.0 - 1.0 / tau) * a_r + b_r);"),
+    "adjoint_transpose_sign": ("double phibar = -2.0 * s * wsc * (Fbx[c] * w.gx[c] + Fby[c] * w.gy[c]) - dax[c] - day[c];",
+                               "double phibar = -2.0 * s * wsc * (Fbx[c] * w.gx[c] + Fby[c] * w.gy[c]) + dax[c] + day[c];"),
+    "adjoint_dropped_local_phi": ("double phibar = -2.0 * s * wsc * (Fbx[c] * w.gx[c] + Fby[c] * w.gy[c]) - dax[c] - day[c];",
+                                  "double phibar = - dax[c] - day[c];"),
+    "adjoint_zc_sign": ("for (size_t c = 0; c < N; ++c) Ubar[c] += dax[c] + day[c];", "for (size_t c = 0; c < N; ++c) Ubar[c] -= dax[c] + day[c];"),
+    "adjoint_momentum_e": ("lam[k * N + c] = (1.0 - 1.0 / tau) * mu[k] + rb + EX[k] * jbx_ + EY[k] * jby_;",
+                           "lam[k * N + c] = (1.0 - 1.0 / tau) * mu[k] + rb + EX[k] * jbx_ + EX[k] * jby_;"),
+    "adjoint_dA_dm": ("*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 3.0 * mx) / rho);", "*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 1.5 * mx) / rho);"),
     "dp_drho_cs": ("return R * T * (Z + e * Zp) - 2.0 * a * rho;", "return R * T * (Z + Zp) - 2.0 * a * rho;"),
 }
 
