@@ -1,0 +1,193 @@
+"""Benchmark of the fused HDM pseudopotential lattice Boltzmann step on one MI355X.
+
+Default workload (the large dynamic case): D2Q9 4096 x 4096 periodic,
+Carnahan-Starling EOS (a = 1, b = 4, R = 1, k = 0.04) at T = 0.5 Tc (density
+ratio ~725), Shan-Chen force with the high-order difference, tau = 1, 400
+seeded droplets with radii uniform in [10, 60] on a vapour background, seeded
+Gaussian velocity noise of std 1e-3.  A step is one launch of the fused kernel
+(density, EOS potential, HDM gradient, force, EDM-BGK collision, periodic
+streaming, and the potential field of the new state).
+
+Output: one JSON line with MLUPS (= nx ny steps / time / 1e6), the roofline of
+the fused kernel against the 8 TB/s HBM peak with algorithmic bytes
+2 Q sizeof(real) per lattice update (every population read once and written
+once), and the FP64 CPU oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import lbm_inputs as I  # noqa: E402
+
+METRIC = "MLUPS & %HBM roofline (FP64/FP32); batched domains/s; adjoint/forward time"
+HBM_PEAK_GBS = 8000.0
+Q = 9
+KERNEL_SOURCES = ["lbm_fused.hpp", "lbm_kernels.hpp", "lbm_device.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1712_06079_amd", "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, seed: int = 2024):
+    """(params kwargs, rho0, ux0, uy0, description) of a named workload."""
+    import paper_1712_06079_amd as L
+    if name == "c5":
+        n = 4096
+        p = L.Params(nx=n, ny=n, eos="cs", force="sc", a=1.0, b=4.0, R=1.0, k=0.04, tau=1.0)
+        tc, _ = L.critical(p)
+        p.T = 0.5 * tc
+        rv, rl, _ = L.maxwell(p, p.T)
+        cx, cy, rr = I.place_droplets(n, n, 400, 10.0, 60.0, 4.0, seed=seed)
+        rho0 = I.droplets(n, n, rv, rl, cx, cy, rr, 4.0)
+        ux0 = I.gaussian((n, n), 1e-3, seed=seed + 1)
+        uy0 = I.gaussian((n, n), 1e-3, seed=seed + 2)
+        desc = "4096x4096 CS T=0.5Tc SC+HDM, 400 droplets R~U[10,60], u noise 1e-3"
+        return p, rho0, ux0, uy0, desc
+    if name == "c2":
+        n = 1024
+        p = L.Params(nx=n, ny=n, eos="cs", force="zc", a=1.0, b=4.0, R=1.0, k=0.04, tau=1.0)
+        tc, _ = L.critical(p)
+        p.T = 0.6 * tc
+        rv, rl, _ = L.maxwell(p, p.T)
+        rho0 = I.droplet(n, n, rv, rl, 128.0, 4.0)
+        desc = "1024x1024 CS T=0.6Tc ZC+HDM droplet R=128 (cache-resident)"
+        return p, rho0, None, None, desc
+    raise ValueError(name)
+
+
+def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0):
+    import torch
+
+    import paper_1712_06079_amd as L
+    p, rho0, ux0, uy0, desc = workload(name)
+    p.prec = prec
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.from_numpy(a).to(dev)  # noqa: E731
+    d = L.Domain(p, t(rho0), t(ux0), t(uy0))
+    d.set_kernel(variant, tile)
+    stream = torch.cuda.current_stream()
+    d.step(warmup)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    total0 = torch.cuda.Event(enable_timing=True)
+    total1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    total0.record(stream)
+    for i in range(steps):
+        starts[i].record(stream)
+        d.step(1)
+        ends[i].record(stream)
+    total1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = total0.elapsed_time(total1)
+    per_launch = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ok = d.check_finite()
+    cells = p.nx * p.ny
+    mlups = cells * steps / (ms_total * 1e-3) / 1e6
+    es = 8 if prec == "f64" else 4
+    alg_bytes = 2 * Q * es * cells  # per launch
+    launch_s = float(np.mean(per_launch)) * 1e-3
+    achieved = alg_bytes / launch_s / 1e9
+    return {
+        "desc": desc, "params": p, "mlups": mlups, "ms_per_step": ms_total / steps, "wall_s": wall,
+        "launch_ms_mean": float(np.mean(per_launch)), "launch_ms_median": float(np.median(per_launch)),
+        "achieved_gbs": achieved, "alg_bytes_per_launch": alg_bytes, "finite": ok,
+    }
+
+
+def traffic_from_profile(name: str, prec: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_fused_{name}_{prec}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(name: str, sample_steps: int):
+    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+    import oracle as O
+    p, rho0, ux0, uy0, _ = workload(name)
+    po = O.Params(nx=p.nx, ny=p.ny, eos=p.eos, force=p.force, grad=p.grad, tau=p.tau, a=p.a, b=p.b, R=p.R,
+                  omega=p.omega, T=p.T, k=p.k, g=p.g, A=p.A)
+    f = O.init(po, rho0, ux0, uy0)
+    t0 = time.perf_counter()
+    O.run(po, f, sample_steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(p.nx * p.ny * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.threads(),
+            "kind": "oracle", "sample": f"{sample_steps} FP64 steps of the {p.nx}x{p.ny} workload ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c5", choices=["c5", "c2"])
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--variant", type=int, default=0, help="0 fused kernel, 1 two-pass reference pair")
+    ap.add_argument("--tile", type=int, default=0, help="rows per fused tile (0 = default)")
+    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle sample steps (0 = skip)")
+    ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: launched with WORLD_SIZE > 1; this build runs on one GPU", file=sys.stderr)
+        sys.exit(2)
+
+    r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile)
+    print(f"[bench] {args.workload} {args.prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
+          f"kernel {r['launch_ms_mean']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    p = r["params"]
+    other = None
+    if not args.no_other_prec:
+        op = "f32" if args.prec == "f64" else "f64"
+        o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile)
+        print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, kernel {o['launch_ms_mean']:.4f} ms, "
+              f"{o['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+        other = {"dtype": op, "value": round(o["mlups"], 1), "ms_per_step": round(o["ms_per_step"], 5),
+                 "roofline_frac": round(o["achieved_gbs"] / HBM_PEAK_GBS, 4), "finite": o["finite"]}
+    cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
+    traffic = traffic_from_profile(args.workload, args.prec)
+    line = {
+        "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": r["desc"], "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
+                   "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": "fused" if args.variant == 0 else "two-pass",
+                   "finite": r["finite"]},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_fused", "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+                     "launch_ms": round(r["launch_ms_mean"], 5)},
+        "cpu_baseline": cpu,
+    }
+    if other:
+        line["other_precision"] = other
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

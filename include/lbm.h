@@ -1,0 +1,158 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) library for the D2Q9 pseudopotential
+ * multiphase lattice Boltzmann step with high-order-difference (HDM) forces,
+ * after Qin, Zhao, Chen, Zhang, Wen, "A pseudopotential multiphase lattice
+ * Boltzmann model based on high-order difference" (arXiv:1712.06079).
+ *
+ * One time step (Sec. 2 Eq. 1) computes, per lattice site:
+ *   density and momentum                                  (Sec. 2 Eq. 3)
+ *   the EOS potential U = g (k p_EOS(rho, T) - rho/3)     (Eq. 8, Hu's scaling of Sec. 5,
+ *        and Phi = sqrt|U| with its sign branch           Eq. 21; EOS: Eqs. 24, 27-29)
+ *   the gradient of Phi (Shan-Chen) or U (Zhang-Chen) by the periodic compact
+ *        sixth-order difference                           (Sec. 3.2 Eq. 20)
+ *   the interaction force F = -2 s Phi grad Phi           (Eq. 22)  or  -grad U (Eq. 7)
+ *   BGK collision with Kupershtokh exact-difference forcing (Eqs. 1, 2, 10)
+ *   periodic streaming                                    (Eq. 1)
+ * The lattice is periodic in x and y with h = dt = 1 and the D2Q9 weights
+ * 4/9, 1/9, 1/36.  G cancels between Eqs. 4 and 6; the parameter g is an
+ * interaction-strength multiplier on U (g = 1 is the paper's model).
+ *
+ * Conventions
+ *  - Memory: every device buffer is owned by the caller.  A domain lives in a
+ *    caller-allocated device workspace of lbm_workspace_bytes(); the handle
+ *    itself is host memory freed by lbm_destroy().  The library never calls
+ *    hipMalloc or hipFree.
+ *  - Streams: every device call is asynchronous on the stream it is given
+ *    (NULL is the null stream).  Errors of an earlier asynchronous launch
+ *    surface at the next call that synchronises.
+ *  - Fields: host-visible field arguments are FP64, row-major [ny][nx]
+ *    (x fastest), device pointers unless stated.  FP32 domains convert on
+ *    entry and exit.
+ *  - Errors: every call returns an lbm_status; lbm_last_error() returns a
+ *    thread-local message describing the last failure.
+ *  - Population order: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1)
+ *    6:(-1,1) 7:(-1,-1) 8:(1,-1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,        /* invalid argument: sizes < 5, tau <= 1/2, null pointer, bad enum, T >= Tc where coexistence is asked */
+    LBM_ENOMEM = 2,        /* workspace smaller than lbm_workspace_bytes() */
+    LBM_EDEVICE = 3,       /* a HIP call failed (message in lbm_last_error) */
+    LBM_ENONFINITE = 4,    /* a non-finite density was found */
+    LBM_EUNSUPPORTED = 5   /* a parameter combination this build does not implement */
+} lbm_status;
+
+typedef enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_CS = 2, LBM_EOS_RK = 3, LBM_EOS_RKS = 4 } lbm_eos;
+typedef enum { LBM_FORCE_SC = 0, LBM_FORCE_ZC = 1, LBM_FORCE_HYBRID = 2 } lbm_force;
+typedef enum { LBM_GRAD_HDM = 0, LBM_GRAD_CDM = 1 } lbm_grad;
+typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
+
+/* Problem statement of one periodic domain (Secs. 2, 4, 5.2).
+ *  nx, ny  lattice size, each >= 5
+ *  eos     equation of state: VDW (Eq. 24), PR (Eq. 28), CS (Eq. 29 read with
+ *          the Carnahan-Starling denominator (1 - b rho/4)^3), RK (Eq. 27,
+ *          alpha = 1/sqrt(T)), RKS (Eq. 27 with the Soave alpha(T_r))
+ *  force   Shan-Chen (Eq. 22), Zhang-Chen (Eq. 7), hybrid (Eq. 9, weight A)
+ *  grad    HDM (Eq. 20) or central difference (Eq. 14)
+ *  prec    storage and arithmetic precision of populations and Phi
+ *  tau     relaxation time (Eq. 1), > 1/2
+ *  a,b,R   EOS constants; omega is the acentric factor (PR, RKS)
+ *  T       absolute temperature (T_r = T / Tc; see lbm_critical)
+ *  k       Hu's EOS scaling p_m = k p_EOS (Sec. 5), > 0
+ *  g       interaction-strength multiplier on U (1 = the paper)
+ *  A       hybrid weight (Eq. 9), used only with LBM_FORCE_HYBRID          */
+typedef struct lbm_params {
+    int32_t nx, ny;
+    int32_t eos, force, grad, prec;
+    double tau;
+    double a, b, R, omega;
+    double T;
+    double k;
+    double g;
+    double A;
+} lbm_params;
+
+typedef struct lbm_domain lbm_domain;
+
+/* Critical point of the EOS in p (host, synchronous): solves dp/drho =
+ * d2p/drho2 = 0 (Sec. 5.2; alpha(Tc) = 1 for PR and RKS).  Independent of k,
+ * g and T.  Returns LBM_EINVAL for bad constants. */
+lbm_status lbm_critical(const lbm_params* p, double* Tc, double* rhoc);
+
+/* Maxwell equal-area coexistence at temperature T (host, synchronous;
+ * Sec. 5.2): rho_v < rho_l with equal pressure and equal chemical potential;
+ * p0 (nullable) receives the unscaled coexistence pressure.  The densities do
+ * not depend on k.  LBM_EINVAL if T >= Tc or T <= 0. */
+lbm_status lbm_maxwell(const lbm_params* p, double T, double* rho_v, double* rho_l, double* p0);
+
+/* Explicit circulant row of the periodic compact difference (Sec. 3.2 Eq. 20)
+ * on n >= 5 points, as the kernels use it (host, synchronous): d[0..*taps-1]
+ * receive d_1..d_taps with (D u)_i = sum_j d_j (u_{i+j} - u_{i-j}); taps =
+ * min(radius, (n-1)/2) with radius 39 for LBM_F64 and 18 for LBM_F32.  d must
+ * hold 40 doubles. */
+lbm_status lbm_hdm_row(int32_t n, int32_t prec, double* d, int32_t* taps);
+
+/* Device workspace needed by one domain with these parameters (bytes). */
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a domain in `workspace` (device, >= lbm_workspace_bytes, 256-byte
+ * aligned, owned by the caller and kept alive until lbm_destroy) and set
+ * f = f^eq(rho0, u0) (Eq. 2).  rho0 is a device FP64 field [ny][nx]; ux0 and
+ * uy0 may be NULL (u0 = 0).  Validates the parameters (LBM_EINVAL) and the
+ * initial density (rho0 must be finite, > 0 and inside the EOS pole: checked
+ * on `stream`, which this call synchronises).  On success *out owns host state
+ * only. */
+lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const double* rho0,
+                    const double* ux0, const double* uy0, hipStream_t stream, lbm_domain** out);
+
+/* Advance the domain by nsteps >= 0 time steps (asynchronous). */
+lbm_status lbm_step(lbm_domain* d, int64_t nsteps, hipStream_t stream);
+
+/* Output moments of the current state (asynchronous): rho (Eq. 3), the
+ * half-step velocity v = (j + F/2)/rho (Eq. 11) and the bulk pressure
+ * p = rho/3 + U.  Any of rho, ux, uy, p may be NULL; each is a device FP64
+ * field [ny][nx].  totals (nullable, device, 4 doubles) receives
+ * {sum rho, sum rho v_x, sum rho v_y, max |v|}, reduced in a fixed order
+ * (bitwise reproducible). */
+lbm_status lbm_moments(lbm_domain* d, double* rho, double* ux, double* uy, double* p, double* totals,
+                       hipStream_t stream);
+
+/* Copy the populations out of / into the domain as a device FP64 array
+ * [9][ny][nx] in the documented velocity order (asynchronous).  set also
+ * refreshes the potential field so the next step sees the new state. */
+lbm_status lbm_get_populations(lbm_domain* d, double* f, hipStream_t stream);
+lbm_status lbm_set_populations(lbm_domain* d, const double* f, hipStream_t stream);
+
+/* Number of steps taken since lbm_init (host). */
+int64_t lbm_step_count(const lbm_domain* d);
+
+/* Select the step kernel (host; for tuning and tests): variant 0 = fused
+ * single-pass kernel, 1 = two-pass reference kernel pair; tile_y = rows per
+ * workgroup tile (0 = default).  LBM_EINVAL for unknown values. */
+lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
+
+/* Check the current density for non-finite values (synchronises `stream`):
+ * *ok = 1 if every rho is finite, else 0 (and the call returns LBM_ENONFINITE). */
+lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream);
+
+/* Free the host state of a domain (the workspace stays with the caller). */
+void lbm_destroy(lbm_domain* d);
+
+/* Thread-local description of the last failure in this thread. */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

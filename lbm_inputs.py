@@ -106,15 +106,20 @@ def place_droplets(nx: int, ny: int, n: int, rmin: float, rmax: float, W: float,
 
 
 def droplets(nx: int, ny: int, rho_v: float, rho_l: float, cx, cy, radii, W: float) -> np.ndarray:
-    """Vapour background plus one tanh droplet per centre (minimum-image distance)."""
-    x = np.arange(nx, dtype=np.float64)[None, :]
-    y = np.arange(ny, dtype=np.float64)[:, None]
+    """Vapour background plus one tanh droplet per centre (minimum-image
+    distance).  Each droplet is added inside its box of half-width R + 12 W,
+    beyond which its tanh term is below 1e-20 of (rho_l - rho_v)."""
     rho = np.full((ny, nx), rho_v, dtype=np.float64)
     for xa, ya, ra in zip(cx, cy, radii):
-        dx = np.abs(x - xa); dx = np.minimum(dx, nx - dx)
-        dy = np.abs(y - ya); dy = np.minimum(dy, ny - dy)
+        h = int(np.ceil(ra + 12 * W))
+        xs = np.arange(int(np.floor(xa)) - h, int(np.floor(xa)) + h + 2)
+        ys = np.arange(int(np.floor(ya)) - h, int(np.floor(ya)) + h + 2)
+        xs = np.unique(xs % nx)
+        ys = np.unique(ys % ny)
+        dx = np.abs(xs[None, :] - xa); dx = np.minimum(dx, nx - dx)
+        dy = np.abs(ys[:, None] - ya); dy = np.minimum(dy, ny - dy)
         r = np.sqrt(dx * dx + dy * dy)
-        rho = rho + 0.5 * (rho_l - rho_v) * (1.0 - np.tanh(2.0 * (r - ra) / W))
+        rho[np.ix_(ys, xs)] += 0.5 * (rho_l - rho_v) * (1.0 - np.tanh(2.0 * (r - ra) / W))
     return np.ascontiguousarray(rho)
 
 

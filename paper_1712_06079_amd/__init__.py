@@ -1,0 +1,211 @@
+"""MI355X (gfx950) HDM pseudopotential lattice Boltzmann library: Python binding.
+
+This module only marshals arguments to the C ABI of ``liblbm_hip.so`` (declared
+in include/lbm.h); every step of the method runs in the library's HIP kernels.
+PyTorch supplies device memory (the workspace and field tensors) and the
+current stream.  Importing works without a GPU; creating a domain needs the
+built library and a GPU and raises if either is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+__all__ = ["Params", "Domain", "LBMError", "library", "critical", "maxwell", "hdm_row", "EOS", "FORCE", "GRAD", "PREC"]
+
+EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
+FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
+GRAD = {"hdm": 0, "cdm": 1}
+PREC = {"f64": 0, "f32": 1}
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_hip.so")
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+class _CParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("eos", C.c_int32), ("force", C.c_int32),
+                ("grad", C.c_int32), ("prec", C.c_int32), ("tau", C.c_double), ("a", C.c_double),
+                ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double), ("T", C.c_double),
+                ("k", C.c_double), ("g", C.c_double), ("A", C.c_double)]
+
+
+@dataclass
+class Params:
+    """Problem statement of one periodic domain (fields as in lbm_params)."""
+    nx: int = 64
+    ny: int = 64
+    eos: str = "vdw"
+    force: str = "sc"
+    grad: str = "hdm"
+    prec: str = "f64"
+    tau: float = 1.0
+    a: float = 9.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    omega: float = 0.344
+    T: float = 0.9 * 4.0 / 7.0
+    k: float = 0.01
+    g: float = 1.0
+    A: float = 0.0
+
+    def c(self) -> _CParams:
+        return _CParams(self.nx, self.ny, EOS[self.eos], FORCE[self.force], GRAD[self.grad], PREC[self.prec],
+                        self.tau, self.a, self.b, self.R, self.omega, self.T, self.k, self.g, self.A)
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def library():
+    """Load liblbm_hip.so (built by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_1712_06079_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(_CParams)
+        D = C.POINTER(C.c_double)
+        L.lbm_critical.argtypes = [P, D, D]
+        L.lbm_maxwell.argtypes = [P, C.c_double, D, D, D]
+        L.lbm_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.lbm_hdm_row.argtypes = [C.c_int32, C.c_int32, D, C.POINTER(C.c_int32)]
+        L.lbm_init.argtypes = [P, _VP, C.c_size_t, _VP, _VP, _VP, _VP, C.POINTER(_VP)]
+        L.lbm_step.argtypes = [_VP, C.c_int64, _VP]
+        L.lbm_moments.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        L.lbm_get_populations.argtypes = [_VP, _VP, _VP]
+        L.lbm_set_populations.argtypes = [_VP, _VP, _VP]
+        L.lbm_step_count.argtypes = [_VP]
+        L.lbm_step_count.restype = C.c_int64
+        L.lbm_set_kernel.argtypes = [_VP, C.c_int32, C.c_int32]
+        L.lbm_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
+        L.lbm_destroy.argtypes = [_VP]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.restype = C.c_char_p
+        for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
+                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_check_finite"):
+            getattr(L, fn).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        raise LBMError(status, library().lbm_last_error().decode())
+
+
+def critical(p: Params):
+    tc, rc = C.c_double(), C.c_double()
+    check(library().lbm_critical(C.byref(p.c()), C.byref(tc), C.byref(rc)))
+    return tc.value, rc.value
+
+
+def maxwell(p: Params, T: float):
+    rv, rl, p0 = C.c_double(), C.c_double(), C.c_double()
+    check(library().lbm_maxwell(C.byref(p.c()), T, C.byref(rv), C.byref(rl), C.byref(p0)))
+    return rv.value, rl.value, p0.value
+
+
+def hdm_row(n: int, prec: str = "f64"):
+    """The explicit coefficients d_1..d_taps of Eq. 20 on n periodic points."""
+    d = (C.c_double * 40)()
+    taps = C.c_int32()
+    check(library().lbm_hdm_row(n, PREC[prec], d, C.byref(taps)))
+    return list(d)[:taps.value]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the HDM LBM library runs on an MI355X only")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Domain:
+    """One periodic domain on the current GPU.
+
+    rho0 (and optional ux0, uy0) are FP64 tensors of shape (ny, nx) on the GPU.
+    """
+
+    def __init__(self, p: Params, rho0, ux0=None, uy0=None, stream=None):
+        torch = _torch()
+        L = library()
+        self.p = p
+        self._cp = p.c()
+        nb = C.c_size_t()
+        check(L.lbm_workspace_bytes(C.byref(self._cp), C.byref(nb)))
+        dev = rho0.device
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nb.value]
+        for t in (rho0, ux0, uy0):
+            if t is not None:
+                assert t.dtype == torch.float64 and t.is_cuda and t.shape == (p.ny, p.nx) and t.is_contiguous()
+        self._keep = (rho0, ux0, uy0)
+        h = C.c_void_p()
+        check(L.lbm_init(C.byref(self._cp), _ptr(self._ws), nb.value, _ptr(rho0), _ptr(ux0), _ptr(uy0),
+                         _stream(stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lbm_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_kernel(self, variant: int = 0, tile_y: int = 0):
+        check(library().lbm_set_kernel(self._h, variant, tile_y))
+
+    def step(self, n: int = 1, stream=None):
+        check(library().lbm_step(self._h, int(n), _stream(stream)))
+
+    @property
+    def steps(self) -> int:
+        return int(library().lbm_step_count(self._h))
+
+    def moments(self, stream=None, want=("rho", "vx", "vy", "p")):
+        torch = _torch()
+        dev = self._ws.device
+        out = {k: torch.empty((self.p.ny, self.p.nx), dtype=torch.float64, device=dev) for k in want}
+        tot = torch.empty(4, dtype=torch.float64, device=dev)
+        check(library().lbm_moments(self._h, _ptr(out.get("rho")), _ptr(out.get("vx")), _ptr(out.get("vy")),
+                                    _ptr(out.get("p")), _ptr(tot), _stream(stream)))
+        out["totals"] = tot
+        return out
+
+    def populations(self, stream=None):
+        torch = _torch()
+        f = torch.empty((9, self.p.ny, self.p.nx), dtype=torch.float64, device=self._ws.device)
+        check(library().lbm_get_populations(self._h, _ptr(f), _stream(stream)))
+        return f
+
+    def set_populations(self, f, stream=None):
+        torch = _torch()
+        assert f.dtype == torch.float64 and f.shape == (9, self.p.ny, self.p.nx) and f.is_contiguous()
+        check(library().lbm_set_populations(self._h, _ptr(f), _stream(stream)))
+
+    def check_finite(self, stream=None) -> bool:
+        ok = C.c_int32()
+        st = library().lbm_check_finite(self._h, C.byref(ok), _stream(stream))
+        if st not in (0, 4):
+            check(st)
+        return bool(ok.value)

@@ -1,0 +1,296 @@
+// HIP kernels of the HDM pseudopotential lattice Boltzmann step (gfx950).
+//
+//   k_init       f = f^eq(rho0, u0) and the potential field of that state
+//   k_phi        potential field phi(rho(f)) of a state
+//   k_collide    two-pass reference step: HDM force from the staged phi cross,
+//                EDM-BGK collision, push streaming (phi refreshed by k_phi)
+//   k_fused      single-pass step (lbm_fused.hpp)
+//   k_moments    rho, half-step velocity, bulk pressure + per-block partials
+//   k_totals     fixed-order reduction of the partials
+//   k_get_f / k_set_f  conversion to and from the documented [9][ny][nx] FP64 layout
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int NT = 256;  // threads per workgroup (four wavefronts)
+
+// ------------------------------------------------------------------ init / phi
+template <typename Real, int FORCE>
+__global__ void __launch_bounds__(NT) k_init(StepArgs<Real> a, const double* __restrict__ rho0,
+                                             const double* __restrict__ ux0, const double* __restrict__ uy0) {
+    const int pitch = a.nxb * BX;
+    const long total = (long)pitch * a.ny;
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < total; c += (long)gridDim.x * NT) {
+        int y = (int)(c / pitch), x = (int)(c - (long)y * pitch);
+        Real* f = a.f_out;
+        if (x < a.nx) {
+            long s = (long)y * a.nx + x;
+            Real rho = (Real)rho0[s];
+            Real ux = ux0 ? (Real)ux0[s] : Real(0), uy = uy0 ? (Real)uy0[s] : Real(0);
+            Real usq = ux * ux + uy * uy;
+            Real fi[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                fi[i] = feq(i, rho, ux, uy, usq);
+                f[fidx(x, y, i, a.nxb)] = fi[i];
+            }
+            Real r, jx, jy;
+            moments(fi, r, jx, jy);
+            a.phi_out[(long)y * pitch + x] = phi_of<Real, FORCE>(potential(a.eos, r));
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[fidx(x, y, i, a.nxb)] = Real(0);
+            a.phi_out[(long)y * pitch + x] = Real(0);
+        }
+    }
+}
+
+template <typename Real, int FORCE>
+__global__ void __launch_bounds__(NT) k_phi(StepArgs<Real> a) {
+    const int pitch = a.nxb * BX;
+    const long total = (long)pitch * a.ny;
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < total; c += (long)gridDim.x * NT) {
+        int y = (int)(c / pitch), x = (int)(c - (long)y * pitch);
+        if (x >= a.nx) continue;
+        Real fi[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fi[i] = a.f_in[fidx(x, y, i, a.nxb)];
+        Real r, jx, jy;
+        moments(fi, r, jx, jy);
+        a.phi_out[(long)y * pitch + x] = phi_of<Real, FORCE>(potential(a.eos, r));
+    }
+}
+
+// ------------------------------------------------------------------ phi cross
+// A 64 x TY tile stages the potential field over its rows widened by +-J in x
+// (for d/dx) and over its columns widened by +-J in y (for d/dy), with
+// periodic wrap.  Rows or columns outside the lattice (ragged tiles) are
+// clamped; they feed only cells that are never written.
+template <typename Real, int TY>
+struct Cross {
+    static constexpr int J = Radius<Real>::value;
+    static constexpr int RW = BX + 2 * J;
+    static constexpr int CH = TY + 2 * J;
+    Real row[TY][RW];
+    Real col[CH][BX];
+};
+
+template <typename Real, int TY>
+__device__ inline void stage_cross(Cross<Real, TY>& s, const Real* __restrict__ phi, int x0, int y0, int nx,
+                                   int ny, int pitch) {
+    using C = Cross<Real, TY>;
+    for (int i = threadIdx.x; i < TY * C::RW; i += NT) {
+        int r = i / C::RW, c = i - r * C::RW;
+        int y = min(y0 + r, ny - 1);
+        int x = wrap(x0 - C::J + c, nx);
+        s.row[r][c] = phi[(long)y * pitch + x];
+    }
+    for (int i = threadIdx.x; i < C::CH * BX; i += NT) {
+        int r = i / BX, c = i - r * BX;
+        int y = wrap(y0 - C::J + r, ny);
+        int x = min(x0 + c, nx - 1);
+        s.col[r][c] = phi[(long)y * pitch + x];
+    }
+}
+
+// Stencil operands: Phi = |phi| (Shan-Chen), U (Zhang-Chen), U = phi |phi| (hybrid's ZC part).
+template <typename Real> __device__ inline Real op_abs(Real v) { return fabs(v); }
+template <typename Real> __device__ inline Real op_sq(Real v) { return v * fabs(v); }
+
+// Interaction force at tile cell (r, lx) from the staged cross:
+//  SC (Eq. 22): F = -2 s Phi D Phi = -2 phi(x) D|phi|
+//  ZC (Eq. 7):  F = -D U
+//  hybrid (Eq. 9): A F^ZC + (1 - 2A) F^SC with U = phi |phi|.
+template <typename Real, int FORCE, int TY>
+__device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& a, int r, int lx, Real& Fx, Real& Fy) {
+    constexpr int J = Cross<Real, TY>::J;
+    const Real pc = s.row[r][J + lx];
+    if (FORCE == FORCE_ZC) {
+        Real gx = 0, gy = 0;
+        for (int j = 1; j <= a.tx; ++j) gx += a.dx[j - 1] * (s.row[r][J + lx + j] - s.row[r][J + lx - j]);
+        for (int j = 1; j <= a.ty; ++j) gy += a.dy[j - 1] * (s.col[J + r + j][lx] - s.col[J + r - j][lx]);
+        Fx = -gx;
+        Fy = -gy;
+    } else {
+        Real gx = 0, gy = 0, ux = 0, uy = 0;
+        for (int j = 1; j <= a.tx; ++j) {
+            Real p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
+            gx += a.dx[j - 1] * (op_abs(p) - op_abs(m));
+            if (FORCE == FORCE_HYBRID) ux += a.dx[j - 1] * (op_sq(p) - op_sq(m));
+        }
+        for (int j = 1; j <= a.ty; ++j) {
+            Real p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
+            gy += a.dy[j - 1] * (op_abs(p) - op_abs(m));
+            if (FORCE == FORCE_HYBRID) uy += a.dy[j - 1] * (op_sq(p) - op_sq(m));
+        }
+        Fx = Real(-2) * pc * gx;
+        Fy = Real(-2) * pc * gy;
+        if (FORCE == FORCE_HYBRID) {
+            Fx = a.A * (-ux) + (Real(1) - Real(2) * a.A) * Fx;
+            Fy = a.A * (-uy) + (Real(1) - Real(2) * a.A) * Fy;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ two-pass reference step
+// Pass 2 of the reference step: per tile, stage phi_t, compute the force,
+// collide and push every population to its downstream neighbour in f_out.
+template <typename Real, int FORCE, int TY>
+__global__ void __launch_bounds__(NT) k_collide(StepArgs<Real> a) {
+    __shared__ Cross<Real, TY> s;
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
+    const int pitch = a.nxb * BX;
+    stage_cross<Real, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    __syncthreads();
+    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
+    for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
+        const int y = y0 + r;
+        if (y >= a.ny) break;
+        Real Fx, Fy;
+        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
+        if (x >= a.nx) continue;
+        Real f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
+        Real rho, jx, jy;
+        moments(f, rho, jx, jy);
+        collide(f, rho, jx, jy, Fx, Fy, a.omega);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xd = x + ex(i), yd = y + ey(i);
+            xd = xd < 0 ? a.nx - 1 : (xd >= a.nx ? 0 : xd);
+            yd = yd < 0 ? a.ny - 1 : (yd >= a.ny ? 0 : yd);
+            a.f_out[fidx(xd, yd, i, a.nxb)] = f[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ moments
+// Output moments (Eq. 3, Eq. 11, p = rho/3 + U) and per-workgroup partials
+// {sum rho, sum rho v_x, sum rho v_y, max |v|} accumulated in FP64 in a fixed
+// order (wavefront butterfly, then the four wavefronts in index order).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename Real, int FORCE, int TY>
+__global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __restrict__ rho_o, double* __restrict__ ux_o,
+                                                double* __restrict__ uy_o, double* __restrict__ p_o,
+                                                double* __restrict__ partial) {
+    __shared__ Cross<Real, TY> s;
+    __shared__ double red[4][NT / BX];
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
+    const int pitch = a.nxb * BX;
+    stage_cross<Real, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    __syncthreads();
+    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
+    double m = 0, px = 0, py = 0, vmax = 0;
+    for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
+        const int y = y0 + r;
+        if (y >= a.ny) break;
+        Real Fx, Fy;
+        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
+        if (x >= a.nx) continue;
+        Real f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
+        Real rho, jx, jy;
+        moments(f, rho, jx, jy);
+        double dr = rho;
+        double vx = ((double)jx + 0.5 * (double)Fx) / dr;
+        double vy = ((double)jy + 0.5 * (double)Fy) / dr;
+        long o = (long)y * a.nx + x;
+        if (rho_o) rho_o[o] = dr;
+        if (ux_o) ux_o[o] = vx;
+        if (uy_o) uy_o[o] = vy;
+        if (p_o) p_o[o] = dr / 3.0 + (double)potential(a.eos, rho);
+        m += dr;
+        px += dr * vx;
+        py += dr * vy;
+        vmax = fmax(vmax, sqrt(vx * vx + vy * vy));
+    }
+    m = wave_sum(m);
+    px = wave_sum(px);
+    py = wave_sum(py);
+    vmax = wave_max(vmax);
+    const int w = threadIdx.x / BX;
+    if ((threadIdx.x & (BX - 1)) == 0) {
+        red[0][w] = m; red[1][w] = px; red[2][w] = py; red[3][w] = vmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        for (int k = 0; k < NT / BX; ++k) {
+            t0 += red[0][k]; t1 += red[1][k]; t2 += red[2][k]; t3 = fmax(t3, red[3][k]);
+        }
+        long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        partial[4 * b + 0] = t0;
+        partial[4 * b + 1] = t1;
+        partial[4 * b + 2] = t2;
+        partial[4 * b + 3] = t3;
+    }
+}
+
+// One workgroup: thread t sums partials t, t + 256, ... in order, then a fixed
+// butterfly and the four wavefronts in index order.
+__global__ void __launch_bounds__(NT) k_totals(const double* __restrict__ partial, long nblocks, double* __restrict__ out) {
+    __shared__ double red[4][NT / BX];
+    double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    for (long b = threadIdx.x; b < nblocks; b += NT) {
+        t0 += partial[4 * b + 0]; t1 += partial[4 * b + 1]; t2 += partial[4 * b + 2];
+        t3 = fmax(t3, partial[4 * b + 3]);
+    }
+    t0 = wave_sum(t0); t1 = wave_sum(t1); t2 = wave_sum(t2); t3 = wave_max(t3);
+    const int w = threadIdx.x / BX;
+    if ((threadIdx.x & (BX - 1)) == 0) { red[0][w] = t0; red[1][w] = t1; red[2][w] = t2; red[3][w] = t3; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int k = 0; k < NT / BX; ++k) { s0 += red[0][k]; s1 += red[1][k]; s2 += red[2][k]; s3 = fmax(s3, red[3][k]); }
+        out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3;
+    }
+}
+
+// ------------------------------------------------------------------ layout conversion
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_get_f(StepArgs<Real> a, double* __restrict__ out) {
+    const long n = (long)a.nx * a.ny;
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
+        int y = (int)(c / a.nx), x = (int)(c - (long)y * a.nx);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[i * n + c] = (double)a.f_in[fidx(x, y, i, a.nxb)];
+    }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_set_f(StepArgs<Real> a, const double* __restrict__ in) {
+    const long n = (long)a.nx * a.ny;
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
+        int y = (int)(c / a.nx), x = (int)(c - (long)y * a.nx);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) a.f_out[fidx(x, y, i, a.nxb)] = (Real)in[i * n + c];
+    }
+}
+
+// Validation of an initial density: flag[0] = 1 if any rho0 is non-finite,
+// <= 0 or at / beyond the pole of the repulsive term.
+__global__ void __launch_bounds__(NT) k_check_rho0(const double* __restrict__ rho0, long n, double rho_max,
+                                                   int* __restrict__ flag) {
+    int bad = 0;
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
+        double r = rho0[c];
+        if (!(r > 0.0) || !(r < rho_max) || !isfinite(r)) bad = 1;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace lbm

@@ -1,0 +1,226 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Bars: FP64 densities within 1e-12 relative, FP32 within 1e-5 relative of the
+FP64 oracle (the tolerance the workload statement fixes); integer-exact
+properties (x-invariance, round trips) bitwise.
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs as I
+import oracle as O
+import oracle_pins as PINS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1712_06079_amd as L  # noqa: E402
+
+VDW_TC = 4.0 / 7.0
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def lib_params(po: O.Params, prec="f64") -> L.Params:
+    return L.Params(nx=po.nx, ny=po.ny, eos=po.eos, force=po.force, grad=po.grad, prec=prec, tau=po.tau, a=po.a,
+                    b=po.b, R=po.R, omega=po.omega, T=po.T, k=po.k, g=po.g, A=po.A)
+
+
+def dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def gpu_run(po, rho0, steps, prec="f64", ux0=None, uy0=None, variant=0, tile=0):
+    d = L.Domain(lib_params(po, prec), dev(rho0), dev(ux0), dev(uy0))
+    d.set_kernel(variant, tile)
+    d.step(steps)
+    m = d.moments()
+    f = d.populations()
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in m.items()}
+    out["f"] = f.cpu().numpy()
+    return out
+
+
+def oracle_run(po, rho0, steps, ux0=None, uy0=None):
+    f = O.run(po, O.init(po, rho0, ux0, uy0), steps)
+    m = O.moments(po, f)
+    m["f"] = f
+    return m
+
+
+def c1_setup():
+    po = PINS.c1_params()
+    rv, rl, _ = O.maxwell(po, po.T)
+    rho0 = I.slab(64, 64, rv, rl, 5.0, axis="y", noise=1e-4, seed=1)
+    return po, rho0
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    po, rho0 = c1_setup()
+    return po, rho0, oracle_run(po, rho0, 2000)
+
+
+@pytest.mark.parametrize("variant,tile", [(0, 0), (0, 4), (0, 16), (1, 8), (1, 16)])
+def test_c1_fp64(c1_oracle, variant, tile):
+    """64x64 VDW T_r = 0.9 slab, SC + HDM, 2000 steps: densities and mass within 1e-12."""
+    po, rho0, ref = c1_oracle
+    got = gpu_run(po, rho0, 2000, "f64", variant=variant, tile=tile)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+    assert abs(got["totals"][0] / ref["rho"].sum() - 1) < 1e-12
+    assert np.max(np.abs(got["f"] - ref["f"])) < 1e-12 * np.max(np.abs(ref["f"]))
+
+
+def test_c1_fp32(c1_oracle):
+    """The same run with FP32 populations and arithmetic: densities within 1e-5."""
+    po, rho0, ref = c1_oracle
+    got = gpu_run(po, rho0, 2000, "f32")
+    err = rel_err(got["rho"], ref["rho"])
+    print(f"C1 FP32 vs FP64 oracle: max rel density error {err:.3e}")
+    assert err < TOL["f32"]
+
+
+def variant_case(eos, force, nx, ny, seed):
+    po = PINS.eos_params(eos)
+    po.nx, po.ny, po.force = nx, ny, force
+    po.A = 0.3 if force == "hybrid" else 0.0
+    tc, _ = O.critical(po)
+    po.T = 0.8 * tc
+    rv, rl, _ = O.maxwell(po, po.T)
+    rho0 = I.droplet(nx, ny, rv, rl, min(nx, ny) / 4.0, 4.0, cx=nx * 0.45, cy=ny * 0.55, noise=1e-3 * rv, seed=seed)
+    ux0 = I.uniform_noise((ny, nx), 1e-3, seed + 1)
+    uy0 = I.uniform_noise((ny, nx), 1e-3, seed + 2)
+    return po, rho0, ux0, uy0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
+@pytest.mark.parametrize("eos", ["vdw", "pr", "cs", "rk", "rks"])
+def test_eos_force_precision(eos, force, prec):
+    """Every EOS x force x precision on a ragged 70 x 37 box (two x-blocks, a
+    partial tile in y), 60 steps, with initial velocity noise."""
+    po, rho0, ux0, uy0 = variant_case(eos, force, 70, 37, seed=5)
+    ref = oracle_run(po, rho0, 60, ux0, uy0)
+    got = gpu_run(po, rho0, 60, prec, ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("nx,ny", [(5, 5), (7, 13), (64, 8), (65, 17), (128, 16), (200, 33), (96, 150), (33, 80)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_shapes(nx, ny, prec):
+    """Small, odd, non-square and ragged lattices (N <= 2J + 1 uses the whole
+    periodic row, N > 2J + 1 the truncated one), 40 steps."""
+    po, rho0, ux0, uy0 = variant_case("cs", "sc", nx, ny, seed=nx * 7 + ny)
+    ref = oracle_run(po, rho0, 40, ux0, uy0)
+    got = gpu_run(po, rho0, 40, prec, ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("variant,tile", [(0, 4), (0, 8), (0, 16), (1, 8), (1, 16)])
+def test_kernel_variants_agree(variant, tile):
+    po, rho0, ux0, uy0 = variant_case("pr", "zc", 150, 70, seed=3)
+    ref = oracle_run(po, rho0, 30, ux0, uy0)
+    got = gpu_run(po, rho0, 30, "f64", ux0, uy0, variant=variant, tile=tile)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+
+
+def test_cdm_gradient():
+    po, rho0, ux0, uy0 = variant_case("vdw", "sc", 70, 37, seed=9)
+    po.grad = "cdm"
+    ref = oracle_run(po, rho0, 60, ux0, uy0)
+    got = gpu_run(po, rho0, 60, "f64", ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_match_oracle(prec):
+    """Half-step velocity (Eq. 11), bulk pressure and the fixed-order totals."""
+    po, rho0, ux0, uy0 = variant_case("vdw", "sc", 96, 80, seed=4)
+    ref = oracle_run(po, rho0, 100, ux0, uy0)
+    got = gpu_run(po, rho0, 100, prec, ux0, uy0)
+    tol = TOL[prec]
+    vscale = max(np.abs(ref["vx"]).max(), np.abs(ref["vy"]).max())
+    assert np.max(np.abs(got["vx"] - ref["vx"])) < 50 * tol * vscale
+    assert np.max(np.abs(got["vy"] - ref["vy"])) < 50 * tol * vscale
+    assert np.max(np.abs(got["p"] - ref["p"])) < 10 * tol * np.abs(ref["p"]).max()
+    t = got["totals"]
+    assert abs(t[0] / ref["rho"].sum() - 1) < tol
+    vmax = np.hypot(ref["vx"], ref["vy"]).max()
+    assert abs(t[3] / vmax - 1) < 50 * tol
+
+
+def test_x_invariance_bitwise():
+    """A noise-free y-slab stays bitwise x-invariant on the GPU (fused kernel,
+    two x-blocks)."""
+    po = PINS.c1_params(nx=128, ny=48)
+    rv, rl, _ = O.maxwell(po, po.T)
+    got = gpu_run(po, I.slab(128, 48, rv, rl, 5.0, axis="y"), 200)
+    f = got["f"]
+    assert np.all(f == f[:, :, :1])
+
+
+def test_totals_bitwise_reproducible():
+    po, rho0, ux0, uy0 = variant_case("cs", "zc", 300, 90, seed=8)
+    a = gpu_run(po, rho0, 20, "f64", ux0, uy0)
+    b = gpu_run(po, rho0, 20, "f64", ux0, uy0)
+    assert np.array_equal(a["totals"], b["totals"]) and np.array_equal(a["f"], b["f"])
+
+
+def test_populations_round_trip():
+    po, rho0, ux0, uy0 = variant_case("vdw", "sc", 40, 30, seed=2)
+    d = L.Domain(lib_params(po), dev(rho0), dev(ux0), dev(uy0))
+    f = O.init(po, rho0, ux0, uy0)
+    assert np.max(np.abs(d.populations().cpu().numpy() - f)) < 1e-14
+    g = O.run(po, f, 7)
+    d.set_populations(dev(g))
+    assert np.array_equal(d.populations().cpu().numpy(), g)
+    d.step(5)
+    ref = O.run(po, g, 5)
+    assert rel_err(d.moments()["rho"].cpu().numpy(), O.moments(po, ref)["rho"]) < 1e-12
+
+
+def test_nonfinite_detected():
+    po, rho0, _, _ = variant_case("vdw", "sc", 40, 30, seed=2)
+    d = L.Domain(lib_params(po), dev(rho0))
+    assert d.check_finite()
+    f = d.populations()
+    f[3, 10, 11] = float("nan")
+    d.set_populations(f)
+    assert not d.check_finite()
+
+
+@pytest.mark.parametrize("bad", ["nan", "negative", "pole"])
+def test_invalid_initial_density_rejected(bad):
+    po, rho0, _, _ = variant_case("vdw", "sc", 40, 30, seed=2)
+    rho0 = rho0.copy()
+    rho0[5, 5] = {"nan": np.nan, "negative": -1.0, "pole": 1.0 / po.b}[bad]
+    with pytest.raises(L.LBMError) as e:
+        L.Domain(lib_params(po), dev(rho0))
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_large_dynamic_case(prec):
+    """4096^2 CS T_r = 0.5 with 400 droplets and velocity noise (the large
+    dynamic workload) in the launch configuration the benchmark times: three
+    steps on the GPU against three oracle steps at full size."""
+    po = PINS.eos_params("cs")
+    tc, _ = O.critical(po)
+    po.nx = po.ny = 4096
+    po.T = 0.5 * tc
+    rv, rl, _ = L.maxwell(lib_params(po), po.T)
+    cx, cy, rr = I.place_droplets(4096, 4096, 400, 10, 60, 4.0, seed=2024)
+    rho0 = I.droplets(4096, 4096, rv, rl, cx, cy, rr, 4.0)
+    ux0 = I.gaussian((4096, 4096), 1e-3, seed=11)
+    uy0 = I.gaussian((4096, 4096), 1e-3, seed=12)
+    got = gpu_run(po, rho0, 3, prec, ux0, uy0)
+    ref = oracle_run(po, rho0, 3, ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+    assert abs(got["totals"][0] / ref["rho"].sum() - 1) < TOL[prec]
