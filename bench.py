@@ -167,15 +167,15 @@ def main():
         o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile)
         print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, kernel {o['launch_ms_mean']:.4f} ms, "
               f"{o['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
-        other = {"dtype": op, "value": round(o["mlups"], 1), "ms_per_step": round(o["ms_per_step"], 5),
+        other = {"storage": op, "dtype": "f64", "value": round(o["mlups"], 1), "ms_per_step": round(o["ms_per_step"], 5),
                  "roofline_frac": round(o["achieved_gbs"] / HBM_PEAK_GBS, 4), "finite": o["finite"]}
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
     traffic = traffic_from_profile(args.workload, args.prec)
     line = {
         "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": r["desc"], "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["desc"], "storage": args.prec, "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
                    "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": "fused" if args.variant == 0 else "two-pass",
                    "finite": r["finite"]},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -146,6 +146,92 @@ lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
  * *ok = 1 if every rho is finite, else 0 (and the call returns LBM_ENONFINITE). */
 lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream);
 
+/* ---- state snapshots (checkpoint / restart) ------------------------------ */
+
+/* Bytes of one snapshot of the domain's populations (device, library layout). */
+lbm_status lbm_state_bytes(const lbm_domain* d, size_t* bytes);
+
+/* Copy the current populations into `state` (device, lbm_state_bytes) /
+ * make `state` the current populations and rebuild its potential field
+ * (asynchronous).  The step counter is not changed. */
+lbm_status lbm_save_state(lbm_domain* d, void* state, hipStream_t stream);
+lbm_status lbm_load_state(lbm_domain* d, const void* state, hipStream_t stream);
+
+/* ---- reverse mode ---------------------------------------------------------- */
+
+/* Device scratch needed by lbm_adjoint_step for this domain (bytes). */
+lbm_status lbm_adjoint_workspace_bytes(const lbm_domain* d, size_t* bytes);
+
+/* One reverse-mode step (asynchronous), the transpose of the Jacobian of the
+ * step of Sec. 2 Eq. 1 (density Eq. 3, potential Eqs. 8 and 21 with Hu's
+ * scaling, gradient Eq. 20, force Eq. 22 or Eq. 7, EDM-BGK collision Eqs. 2
+ * and 10, streaming) at the state `state_t` (a snapshot from lbm_save_state):
+ *   lam_t = (d f_{t+1} / d f_t)^T lam_next,
+ *   grad[0] += dJ/dg,  grad[1] += dJ/dT   (J the objective whose dJ/df_{t+1} is lam_next).
+ * lam_next, lam_t: device FP64 [9][ny][nx] (distinct buffers); grad: device,
+ * 2 doubles; adj_ws: device scratch of lbm_adjoint_workspace_bytes, 256-byte
+ * aligned.  The domain's own state is not touched.  LBM_EUNSUPPORTED for FP32
+ * domains and for the hybrid force. */
+lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, double* grad,
+                            void* adj_ws, size_t adj_ws_bytes, hipStream_t stream);
+
+/* dJ/drho0 from dJ/df_0 for the initial state f_0 = f^eq(rho0, u0) of Eq. 2 at
+ * fixed u0 (asynchronous): drho0 = sum_i lam0_i f^eq_i(1, u0).  lam0 device
+ * FP64 [9][ny][nx]; ux0, uy0 device [ny][nx] or NULL (u0 = 0); drho0 device [ny][nx]. */
+lbm_status lbm_adjoint_rho0(lbm_domain* d, const double* lam0, const double* ux0, const double* uy0, double* drho0,
+                            hipStream_t stream);
+
+/* ---- batched sweep ------------------------------------------------------- */
+
+/* Many independent periodic domains that differ in size, EOS, temperature
+ * and constants (the coexistence-curve sweep of Sec. 5.2, Fig. 5) but share
+ * precision and force, advanced together: one launch per step of a worklist
+ * kernel whose tiles cover every domain, replayed from a captured hipGraph.
+ * A scheduler setting (tile height, worklist order, workgroups of the
+ * persistent launch) is picked by lbm_batch_autotune. */
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace for a batch of n >= 1 domains (bytes). */
+lbm_status lbm_batch_workspace_bytes(const lbm_params* params, int32_t n, size_t* bytes);
+
+/* Create a batch in `workspace` (device, 256-byte aligned, caller-owned, kept
+ * until lbm_batch_destroy) with domain i = params[i] initialised to
+ * f^eq(rho0s[i], 0) (Eq. 2).  rho0s is a host array of n device pointers to
+ * FP64 fields [ny_i][nx_i].  Validates like lbm_init; synchronises `stream`. */
+lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace, size_t workspace_bytes,
+                            const double* const* rho0s, hipStream_t stream, lbm_batch** out);
+
+/* Advance every domain by nsteps: one batched launch per step, in captured
+ * graphs of 16 launches (asynchronous). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, hipStream_t stream);
+
+/* The same evolution with one single-domain fused launch per domain per step
+ * (the plain path the batched launch is measured against; asynchronous). */
+lbm_status lbm_batch_step_separate(lbm_batch* b, int64_t nsteps, hipStream_t stream);
+
+/* Handle of domain i for lbm_moments, lbm_get_populations, lbm_check_finite
+ * (owned by the batch; NULL if i is out of range). */
+lbm_domain* lbm_batch_domain(lbm_batch* b, int32_t i);
+
+/* Scheduler setting: tile_y rows per tile (4 or 8), order (0 = domain order,
+ * 1 = largest domains first, 2 = round robin over domains), grid = workgroups
+ * of the persistent launch (0 = one per tile).  set synchronises the null stream. */
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid);
+lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* order, int32_t* grid);
+
+/* Time every scheduler candidate over probe_steps batched steps with HIP
+ * events, keep the fastest, and restore every domain's state as it was on
+ * entry (synchronises `stream`).  report (nullable) receives a JSON object of
+ * the per-step times in ms and the choice. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t stream, char* report, size_t report_len);
+
+/* Per-domain non-finite check (synchronises): flags[i] = 1 if domain i holds a
+ * non-finite density (host array of n int32); returns LBM_ENONFINITE if any. */
+lbm_status lbm_batch_check_finite(lbm_batch* b, int32_t* flags, hipStream_t stream);
+
+/* Free the host state of a batch and its domains (the workspace stays with the caller). */
+void lbm_batch_destroy(lbm_batch* b);
+
 /* Free the host state of a domain (the workspace stays with the caller). */
 void lbm_destroy(lbm_domain* d);
 

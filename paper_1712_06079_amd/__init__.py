@@ -12,7 +12,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
-__all__ = ["Params", "Domain", "LBMError", "library", "critical", "maxwell", "hdm_row", "EOS", "FORCE", "GRAD", "PREC"]
+__all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxwell", "hdm_row", "EOS", "FORCE", "GRAD", "PREC"]
 
 EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
 FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
@@ -84,11 +84,19 @@ def library():
         L.lbm_step_count.restype = C.c_int64
         L.lbm_set_kernel.argtypes = [_VP, C.c_int32, C.c_int32]
         L.lbm_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
+        L.lbm_state_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
+        L.lbm_save_state.argtypes = [_VP, _VP, _VP]
+        L.lbm_load_state.argtypes = [_VP, _VP, _VP]
+        L.lbm_adjoint_workspace_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
+        L.lbm_adjoint_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+        L.lbm_adjoint_rho0.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
         L.lbm_destroy.argtypes = [_VP]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
-                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_check_finite"):
+                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_check_finite",
+                   "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
+                   "lbm_adjoint_step", "lbm_adjoint_rho0"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -209,3 +217,148 @@ class Domain:
         if st not in (0, 4):
             check(st)
         return bool(ok.value)
+
+    # ---- snapshots and reverse mode -------------------------------------------------
+    def state_bytes(self) -> int:
+        nb = C.c_size_t()
+        check(library().lbm_state_bytes(self._h, C.byref(nb)))
+        return nb.value
+
+    def new_states(self, n: int):
+        """Device storage for n state snapshots (uint8 tensor [n, state_bytes], rows 256-byte aligned)."""
+        torch = _torch()
+        sb = self.state_bytes()
+        return torch.empty((n, sb), dtype=torch.uint8, device=self._ws.device)
+
+    def save_state(self, state, stream=None):
+        check(library().lbm_save_state(self._h, _ptr(state), _stream(stream)))
+
+    def load_state(self, state, stream=None):
+        check(library().lbm_load_state(self._h, _ptr(state), _stream(stream)))
+
+    def adjoint_workspace(self):
+        torch = _torch()
+        nb = C.c_size_t()
+        check(library().lbm_adjoint_workspace_bytes(self._h, C.byref(nb)))
+        return torch.empty(nb.value, dtype=torch.uint8, device=self._ws.device)
+
+    def adjoint_step(self, state, lam_next, lam, grad, adj_ws, stream=None):
+        """lam = (d step / d f_t)^T lam_next at `state`; grad[0] += dJ/dg, grad[1] += dJ/dT."""
+        check(library().lbm_adjoint_step(self._h, _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(grad), _ptr(adj_ws),
+                                         adj_ws.numel(), _stream(stream)))
+
+    def adjoint_rho0(self, lam0, ux0=None, uy0=None, stream=None):
+        torch = _torch()
+        out = torch.empty((self.p.ny, self.p.nx), dtype=torch.float64, device=self._ws.device)
+        check(library().lbm_adjoint_rho0(self._h, _ptr(lam0), _ptr(ux0), _ptr(uy0), _ptr(out), _stream(stream)))
+        return out
+
+
+class _DomainView(Domain):
+    """A domain owned by a Batch (borrowed handle; not destroyed on deletion)."""
+
+    def __init__(self, batch, handle, p: Params):
+        self._batch = batch
+        self.p = p
+        self._h = handle
+        self._ws = batch._ws
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """Many independent periodic domains stepped by one launch per step.
+
+    params: list of Params (same prec and force); rho0s: list of FP64 CUDA
+    tensors of shape (ny_i, nx_i).
+    """
+
+    _SIGS_DONE = False
+
+    @classmethod
+    def _sigs(cls):
+        L = library()
+        if cls._SIGS_DONE:
+            return L
+        P = C.POINTER(_CParams)
+        L.lbm_batch_workspace_bytes.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+        L.lbm_batch_create.argtypes = [P, C.c_int32, _VP, C.c_size_t, C.POINTER(_VP), _VP, C.POINTER(_VP)]
+        L.lbm_batch_step.argtypes = [_VP, C.c_int64, _VP]
+        L.lbm_batch_step_separate.argtypes = [_VP, C.c_int64, _VP]
+        L.lbm_batch_domain.argtypes = [_VP, C.c_int32]
+        L.lbm_batch_domain.restype = _VP
+        L.lbm_batch_set_schedule.argtypes = [_VP, C.c_int32, C.c_int32, C.c_int32]
+        L.lbm_batch_get_schedule.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.lbm_batch_autotune.argtypes = [_VP, C.c_int32, _VP, C.c_char_p, C.c_size_t]
+        L.lbm_batch_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
+        L.lbm_batch_destroy.argtypes = [_VP]
+        L.lbm_batch_destroy.restype = None
+        for fn in ("lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_separate",
+                   "lbm_batch_set_schedule", "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_check_finite"):
+            getattr(L, fn).restype = C.c_int
+        cls._SIGS_DONE = True
+        return L
+
+    def __init__(self, params, rho0s, stream=None):
+        torch = _torch()
+        L = self._sigs()
+        n = len(params)
+        assert n == len(rho0s) and n >= 1
+        self.params = list(params)
+        self._cp = (_CParams * n)(*[p.c() for p in params])
+        nb = C.c_size_t()
+        check(L.lbm_batch_workspace_bytes(self._cp, n, C.byref(nb)))
+        dev = rho0s[0].device
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nb.value]
+        for p, t in zip(params, rho0s):
+            assert t.dtype == torch.float64 and t.is_cuda and t.shape == (p.ny, p.nx) and t.is_contiguous()
+        self._keep = list(rho0s)
+        ptrs = (_VP * n)(*[t.data_ptr() for t in rho0s])
+        h = C.c_void_p()
+        check(L.lbm_batch_create(self._cp, n, _ptr(self._ws), nb.value, ptrs, _stream(stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lbm_batch_destroy(h)
+            self._h = None
+
+    def __len__(self):
+        return len(self.params)
+
+    def step(self, n: int = 1, stream=None):
+        check(self._sigs().lbm_batch_step(self._h, int(n), _stream(stream)))
+
+    def step_separate(self, n: int = 1, stream=None):
+        check(self._sigs().lbm_batch_step_separate(self._h, int(n), _stream(stream)))
+
+    def domain(self, i: int) -> Domain:
+        h = self._sigs().lbm_batch_domain(self._h, int(i))
+        if not h:
+            raise IndexError(i)
+        return _DomainView(self, C.c_void_p(h), self.params[i])
+
+    def set_schedule(self, tile_y: int, order: int, grid: int):
+        check(self._sigs().lbm_batch_set_schedule(self._h, tile_y, order, grid))
+
+    def schedule(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(self._sigs().lbm_batch_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"tile_y": a.value, "order": b.value, "grid": c.value}
+
+    def autotune(self, probe_steps: int = 20, stream=None) -> dict:
+        import json
+        buf = C.create_string_buffer(8192)
+        check(self._sigs().lbm_batch_autotune(self._h, probe_steps, _stream(stream), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def check_finite(self, stream=None):
+        flags = (C.c_int32 * len(self.params))()
+        st = self._sigs().lbm_batch_check_finite(self._h, flags, _stream(stream))
+        if st not in (0, 4):
+            check(st)
+        return [bool(f) for f in flags]

@@ -1,0 +1,70 @@
+"""Differentiable rollout of the HDM lattice Boltzmann step on the GPU.
+
+``HDMRollout.apply(rho0, g, T, params, nsteps, every)`` returns the density
+after ``nsteps`` steps from f = f^eq(rho0, 0).  Its backward pass is the
+library's hand-written adjoint step (lbm_adjoint_step) driven in reverse with
+sqrt(N)-style checkpointing: the forward pass keeps one state snapshot every
+``every`` steps; the backward pass reloads each snapshot, recomputes its
+segment (keeping those ``every`` states) and runs the adjoint steps in reverse
+order.  Memory: (ceil(nsteps / every) + every) snapshots.  Gradients flow to
+rho0, to the interaction multiplier g and to the temperature T.
+"""
+import dataclasses
+import math
+
+import torch
+
+from . import Domain, Params
+
+
+class HDMRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho0, g, T, params: Params, nsteps: int, every: int = 70):
+        p = dataclasses.replace(params, g=float(g), T=float(T), prec="f64")
+        d = Domain(p, rho0.detach().contiguous())
+        nseg = max(1, math.ceil(nsteps / every))
+        ck = d.new_states(nseg)
+        for s in range(nsteps):
+            if s % every == 0:
+                d.save_state(ck[s // every])
+            d.step(1)
+        if nsteps == 0:
+            d.save_state(ck[0])
+        rho = d.moments(want=("rho",))["rho"]
+        ctx.d, ctx.ck, ctx.nsteps, ctx.every = d, ck, nsteps, every
+        ctx.g_dev, ctx.T_dev = g, T
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        d, ck, nsteps, every = ctx.d, ctx.ck, ctx.nsteps, ctx.every
+        ny, nx = grad_rho.shape
+        # rho = sum_i f_i, so dJ/df_i = dJ/drho for every population
+        lam = grad_rho.detach().to(torch.float64).expand(9, ny, nx).contiguous()
+        lam2 = torch.empty_like(lam)
+        grad = torch.zeros(2, dtype=torch.float64, device=lam.device)
+        ws = d.adjoint_workspace()
+        seg = d.new_states(min(every, max(nsteps, 1)))
+        nseg = max(1, math.ceil(nsteps / every))
+        for sidx in reversed(range(nseg)):
+            t0, t1 = sidx * every, min(nsteps, sidx * every + every)
+            if t1 <= t0:
+                continue
+            d.load_state(ck[sidx])
+            for t in range(t0, t1):
+                d.save_state(seg[t - t0])
+                d.step(1)
+            for t in reversed(range(t0, t1)):
+                d.adjoint_step(seg[t - t0], lam, lam2, grad, ws)
+                lam, lam2 = lam2, lam
+        drho0 = d.adjoint_rho0(lam)
+
+        def like(v, ref):
+            return v.to(dtype=ref.dtype, device=ref.device).reshape(ref.shape) if torch.is_tensor(ref) else None
+
+        return drho0, like(grad[0], ctx.g_dev), like(grad[1], ctx.T_dev), None, None, None
+
+
+def rollout(rho0, g, T, params: Params, nsteps: int, every: int = 70):
+    """Density after nsteps steps, differentiable in rho0, g and T."""
+    return HDMRollout.apply(rho0, g, T, params, nsteps, every)

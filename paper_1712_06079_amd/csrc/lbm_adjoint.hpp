@@ -1,0 +1,262 @@
+// Reverse-mode (adjoint) step of the HDM pseudopotential lattice Boltzmann
+// step, FP64, Shan-Chen or Zhang-Chen force.
+//
+// With the equilibrium in momentum form A_i(rho, m) = w_i [rho + 3 e.m +
+// (4.5 (e.m)^2 - 1.5 |m|^2)/rho], one step is
+//   f*_i = (1 - w) f_i + (w - 1) A_i(rho, j) + A_i(rho, j + F),  w = 1/tau,
+//   f_{t+1,i}(x + e_i) = f*_i(x)                       (Eqs. 1, 2, 3, 10)
+// and the force is F = -2 phi D|phi| (Eq. 22, phi = s Phi) or F = -D U
+// (Eq. 7), D the circulant form of Eq. 20 along each axis.  Given
+// lam = dJ/df_{t+1} (layout [9][ny][nx]) the adjoint is
+//   mu_i(x)   = lam_i(x + e_i)
+//   rho_bar   = sum_i mu_i [(w - 1) dA_i/drho(rho, j) + dA_i/drho(rho, j + F)]
+//   j_bar     = sum_i mu_i [(w - 1) dA_i/dm(rho, j)   + dA_i/dm(rho, j + F)]
+//   F_bar     = sum_i mu_i dA_i/dm(rho, j + F)
+//   SC: U_bar = -(F_bar . D Phi)/Phi + s/(2 Phi) * (-D_x a_x - D_y a_y),  a = -2 phi F_bar
+//   ZC: U_bar = D_x F_bar_x + D_y F_bar_y                 (D^T = -D)
+//   dJ/df_k(x) = (1 - w) mu_k + rho_bar + e_k . j_bar + U_bar dU/drho
+//   dJ/dg += sum U_bar dU/dg,   dJ/dT += sum U_bar dU/dT.
+// Pass 1 (k_adj_local) does everything local to a cell and writes the planes
+// a_x, a_y, U_bar_local and rho; pass 2 (k_adj_nonlocal) applies D to the a
+// planes from an LDS cross, finishes U_bar and adds the density term.
+#pragma once
+
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+// Constants of U = g (k p_EOS - rho/3) and its derivatives, unscaled by g so
+// that dU/dg is available: U = g (c_rep rep(rho) - c_att att(rho) - rho/3),
+// dU/dT = g (k R rep(rho) - c_attT att(rho)) with c_attT = k a alpha'(T).
+struct AdjEos {
+    int kind;
+    double g, b, c_rep, c_att, c_attT, kR;
+};
+
+__device__ inline void eos_parts(int kind, double b, double rho, double& rep, double& drep, double& att, double& datt) {
+    if (kind == EOS_CS) {
+        const double eta = 0.25 * b * rho, om = 1.0 - eta;
+        const double N = 1.0 + eta * (1.0 + eta * (1.0 - eta));
+        const double Np = 1.0 + eta * (2.0 - 3.0 * eta);
+        const double om3 = om * om * om;
+        const double Z = N / om3, Zp = Np / om3 + 3.0 * N / (om3 * om);
+        rep = rho * Z;
+        drep = Z + eta * Zp;
+        att = rho * rho;
+        datt = 2.0 * rho;
+        return;
+    }
+    const double ob = 1.0 - b * rho;
+    rep = rho / ob;
+    drep = 1.0 / (ob * ob);
+    if (kind == EOS_PR) {
+        const double q = 1.0 + b * rho * (2.0 - b * rho), qp = 2.0 * b * (1.0 - b * rho);
+        att = rho * rho / q;
+        datt = (2.0 * rho * q - rho * rho * qp) / (q * q);
+    } else if (kind == EOS_RK || kind == EOS_RKS) {
+        const double s = 1.0 + b * rho;
+        att = rho * rho / s;
+        datt = rho * (2.0 + b * rho) / (s * s);
+    } else {
+        att = rho * rho;
+        datt = 2.0 * rho;
+    }
+}
+
+__device__ inline void dA(int i, double rho, double ir, double mx, double my, double& dr, double& dmx, double& dmy) {
+    const double em = double(ex(i)) * mx + double(ey(i)) * my;
+    const double m2 = mx * mx + my * my;
+    const double w = wq<double>(i);
+    dr = w * (1.0 - (4.5 * em * em - 1.5 * m2) * ir * ir);
+    dmx = w * (3.0 * double(ex(i)) + (9.0 * em * double(ex(i)) - 3.0 * mx) * ir);
+    dmy = w * (3.0 * double(ey(i)) + (9.0 * em * double(ey(i)) - 3.0 * my) * ir);
+}
+
+struct AdjArgs {
+    StepArgs<double> s;             // f_in = state f_t, phi_in = phi(f_t), tables
+    const double* __restrict__ lam_next;  // [9][ny][nx]
+    double* __restrict__ lam;             // [9][ny][nx]
+    double* __restrict__ ax;              // [ny][pitch]
+    double* __restrict__ ay;
+    double* __restrict__ ubl;             // U_bar local part
+    double* __restrict__ rho;
+    double* __restrict__ partial;         // [blocks][2]
+    AdjEos e;
+};
+
+// Pass 1: per 64 x TY tile, stage phi_t, recompute F and D Phi, pull lam_next,
+// local adjoint of collision and force.
+template <int FORCE, int TY>
+__global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
+    __shared__ Cross<double, TY> s;
+    const StepArgs<double>& a = A.s;
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
+    const int pitch = a.nxb * BX;
+    const long n = (long)a.nx * a.ny;
+    stage_cross<double, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    __syncthreads();
+    constexpr int J = Cross<double, TY>::J;
+    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
+    for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
+        const int y = y0 + r;
+        if (y >= a.ny) break;
+        const double pc = s.row[r][J + lx];
+        double gx = 0, gy = 0;
+        for (int j = 1; j <= a.tx; ++j) {
+            const double p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
+            gx += a.dx[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
+        }
+        for (int j = 1; j <= a.ty; ++j) {
+            const double p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
+            gy += a.dy[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
+        }
+        if (x >= a.nx) continue;
+        const double Fx = FORCE == FORCE_ZC ? -gx : -2.0 * pc * gx;
+        const double Fy = FORCE == FORCE_ZC ? -gy : -2.0 * pc * gy;
+        double f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
+        double rho, jx, jy;
+        moments(f, rho, jx, jy);
+        const double ir = 1.0 / rho, w = a.omega;
+        const double mx = jx + Fx, my = jy + Fy;
+        double mu[Q];
+        double rb = 0, jbx = 0, jby = 0, fbx = 0, fby = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xs = x + ex(i), ys = y + ey(i);
+            xs = xs < 0 ? a.nx - 1 : (xs >= a.nx ? 0 : xs);
+            ys = ys < 0 ? a.ny - 1 : (ys >= a.ny ? 0 : ys);
+            mu[i] = A.lam_next[i * n + (long)ys * a.nx + xs];
+            double ar, axx, ayy, br, bx, by;
+            dA(i, rho, ir, jx, jy, ar, axx, ayy);
+            dA(i, rho, ir, mx, my, br, bx, by);
+            rb += mu[i] * ((w - 1.0) * ar + br);
+            jbx += mu[i] * ((w - 1.0) * axx + bx);
+            jby += mu[i] * ((w - 1.0) * ayy + by);
+            fbx += mu[i] * bx;
+            fby += mu[i] * by;
+        }
+        const long o = (long)y * a.nx + x;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) A.lam[k * n + o] = (1.0 - w) * mu[k] + rb + double(ex(k)) * jbx + double(ey(k)) * jby;
+        const long op = (long)y * pitch + x;
+        if (FORCE == FORCE_ZC) {
+            A.ax[op] = fbx;
+            A.ay[op] = fby;
+            A.ubl[op] = 0.0;
+        } else {
+            const double Phi = fabs(pc);
+            A.ax[op] = -2.0 * pc * fbx;
+            A.ay[op] = -2.0 * pc * fby;
+            A.ubl[op] = -(fbx * gx + fby * gy) / Phi;
+        }
+        A.rho[op] = rho;
+    }
+}
+
+// Pass 2: D applied to the a planes (staged like phi), U_bar, density term,
+// parameter partials per workgroup (fixed order).
+template <int FORCE, int TY>
+__global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
+    __shared__ Cross<double, TY> sx;   // row bar of a_x (col bar unused)
+    __shared__ Cross<double, TY> sy;   // col bar of a_y (row bar unused)
+    __shared__ double red[2][NT / BX];
+    const StepArgs<double>& a = A.s;
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
+    const int pitch = a.nxb * BX;
+    const long n = (long)a.nx * a.ny;
+    using C = Cross<double, TY>;
+    for (int i = threadIdx.x; i < TY * C::RW; i += NT) {
+        int r = i / C::RW, c = i - r * C::RW;
+        int y = min(y0 + r, a.ny - 1);
+        int xw = wrap(x0 - C::J + c, a.nx);
+        sx.row[r][c] = A.ax[(long)y * pitch + xw];
+    }
+    for (int i = threadIdx.x; i < C::CH * BX; i += NT) {
+        int r = i / BX, c = i - r * BX;
+        int yw = wrap(y0 - C::J + r, a.ny);
+        int xx = min(x0 + c, a.nx - 1);
+        sy.col[r][c] = A.ay[(long)yw * pitch + xx];
+    }
+    __syncthreads();
+    constexpr int J = C::J;
+    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
+    double sg = 0.0, sT = 0.0;
+    for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
+        const int y = y0 + r;
+        if (y >= a.ny) break;
+        double dxa = 0, dya = 0;
+        for (int j = 1; j <= a.tx; ++j) dxa += a.dx[j - 1] * (sx.row[r][J + lx + j] - sx.row[r][J + lx - j]);
+        for (int j = 1; j <= a.ty; ++j) dya += a.dy[j - 1] * (sy.col[J + r + j][lx] - sy.col[J + r - j][lx]);
+        if (x >= a.nx) continue;
+        const long op = (long)y * pitch + x;
+        double ub;
+        if (FORCE == FORCE_ZC) {
+            ub = dxa + dya;
+        } else {
+            const double ph = a.phi_in[op];
+            const double sgn = ph < 0.0 ? -1.0 : 1.0;
+            ub = A.ubl[op] + sgn / (2.0 * fabs(ph)) * (-dxa - dya);
+        }
+        const double rho = A.rho[op];
+        double rep, drep, att, datt;
+        eos_parts(A.e.kind, A.e.b, rho, rep, drep, att, datt);
+        const double dUdrho = A.e.g * (A.e.c_rep * drep - A.e.c_att * datt - 1.0 / 3.0);
+        const double dUdg = A.e.c_rep * rep - A.e.c_att * att - rho / 3.0;
+        const double dUdT = A.e.g * (A.e.kR * rep - A.e.c_attT * att);
+        const double add = ub * dUdrho;
+        const long o = (long)y * a.nx + x;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) A.lam[k * n + o] += add;
+        sg += ub * dUdg;
+        sT += ub * dUdT;
+    }
+    sg = wave_sum(sg);
+    sT = wave_sum(sT);
+    const int w = threadIdx.x / BX;
+    if ((threadIdx.x & (BX - 1)) == 0) { red[0][w] = sg; red[1][w] = sT; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0, t1 = 0;
+        for (int k = 0; k < NT / BX; ++k) { t0 += red[0][k]; t1 += red[1][k]; }
+        const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        A.partial[2 * b] = t0;
+        A.partial[2 * b + 1] = t1;
+    }
+}
+
+// grad[0..1] += fixed-order sums of the pass-2 partials (one workgroup).
+static __global__ void __launch_bounds__(NT) k_adj_accumulate(const double* __restrict__ partial, long nblocks,
+                                                       double* __restrict__ grad) {
+    __shared__ double red[2][NT / BX];
+    double t0 = 0, t1 = 0;
+    for (long b = threadIdx.x; b < nblocks; b += NT) { t0 += partial[2 * b]; t1 += partial[2 * b + 1]; }
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    const int w = threadIdx.x / BX;
+    if ((threadIdx.x & (BX - 1)) == 0) { red[0][w] = t0; red[1][w] = t1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0;
+        for (int k = 0; k < NT / BX; ++k) { s0 += red[0][k]; s1 += red[1][k]; }
+        grad[0] += s0;
+        grad[1] += s1;
+    }
+}
+
+// dJ/drho0 = sum_i lam0_i f^eq_i(rho0, u0) / rho0 (f^eq is linear in rho at fixed u).
+static __global__ void __launch_bounds__(NT) k_adj_rho0(const double* __restrict__ lam0, const double* __restrict__ rho0,
+                                                 const double* __restrict__ ux0, const double* __restrict__ uy0,
+                                                 long n, double* __restrict__ out) {
+    for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
+        const double ux = ux0 ? ux0[c] : 0.0, uy = uy0 ? uy0[c] : 0.0;
+        const double usq = ux * ux + uy * uy;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc += lam0[i * n + c] * feq(i, 1.0, ux, uy, usq);
+        out[c] = acc;
+    }
+}
+
+}  // namespace lbm

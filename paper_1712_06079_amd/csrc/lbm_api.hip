@@ -13,12 +13,18 @@
 #include "../../include/lbm.h"
 #include "eos_host.hpp"
 #include "hdm_coeffs.hpp"
+#include "lbm_adjoint.hpp"
 #include "lbm_fused.hpp"
+#include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 
 namespace {
 
 thread_local char g_err[512] = "";
+
+}  // namespace
+
+namespace lbm_internal {
 
 lbm_status fail(lbm_status s, const char* fmt, ...) {
     va_list ap;
@@ -28,13 +34,11 @@ lbm_status fail(lbm_status s, const char* fmt, ...) {
     return s;
 }
 
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess) return fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace lbm_internal
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+using namespace lbm_internal;
+
+namespace {
 
 lbm_host::EosConst eos_const(const lbm_params* p) {
     return lbm_host::EosConst{p->eos, p->a, p->b, p->R, p->omega};
@@ -59,24 +63,6 @@ lbm_status validate(const lbm_params* p) {
 
 int nblocks_x(int nx) { return (nx + lbm::BX - 1) / lbm::BX; }
 
-}  // namespace
-
-struct lbm_domain {
-    lbm_params p;
-    double Tc, rhoc, alpha;
-    int nxb, pitch;
-    int cur;           // index of the buffer pair holding the current state
-    int64_t steps;
-    int variant;       // 0 fused, 1 two-pass reference
-    int tile_y;        // fused: rows per tile; reference: rows per tile
-    char* ws;
-    size_t ws_bytes;
-    size_t off_f[2], off_phi[2], off_part, off_scr;
-    int tx, ty;
-    double dx[lbm::JCAP], dy[lbm::JCAP];
-};
-
-namespace {
 
 struct Layout {
     size_t f, phi, part, scr, total;
@@ -89,7 +75,7 @@ Layout layout_of(const lbm_params* p) {
     const size_t pitch = (size_t)nblocks_x(p->nx) * lbm::BX;
     Layout L;
     L.f = align256(lbm::Q * pitch * p->ny * es);
-    L.phi = align256(pitch * p->ny * es);
+    L.phi = align256(pitch * p->ny * sizeof(double));
     const size_t nb = (size_t)nblocks_x(p->nx) * ((p->ny + MOM_TY - 1) / MOM_TY);
     L.part = align256(nb * 4 * sizeof(double));
     L.scr = 256;
@@ -97,59 +83,9 @@ Layout layout_of(const lbm_params* p) {
     return L;
 }
 
-template <typename Real>
-lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
-    lbm::StepArgs<Real> a;
-    std::memset(&a, 0, sizeof(a));
-    a.f_in = reinterpret_cast<const Real*>(d->ws + d->off_f[in_buf]);
-    a.f_out = reinterpret_cast<Real*>(d->ws + d->off_f[out_buf]);
-    a.phi_in = reinterpret_cast<const Real*>(d->ws + d->off_phi[in_buf]);
-    a.phi_out = reinterpret_cast<Real*>(d->ws + d->off_phi[out_buf]);
-    a.nx = d->p.nx;
-    a.ny = d->p.ny;
-    a.nxb = d->nxb;
-    a.tx = d->tx;
-    a.ty = d->ty;
-    a.omega = (Real)(1.0 / d->p.tau);
-    a.A = (Real)d->p.A;
-    const double g = d->p.g, k = d->p.k;
-    a.eos.kind = d->p.eos;
-    a.eos.c_rep = (Real)(g * k * d->p.R * d->p.T);
-    a.eos.c_att = (Real)(g * k * d->p.a * d->alpha);
-    a.eos.c_lin = (Real)(g / 3.0);
-    a.eos.b = (Real)d->p.b;
-    for (int j = 0; j < lbm::JCAP; ++j) {
-        a.dx[j] = (Real)d->dx[j];
-        a.dy[j] = (Real)d->dy[j];
-    }
-    return a;
-}
+}  // namespace
 
-unsigned grid_1d(long n) {
-    long b = (n + lbm::NT - 1) / lbm::NT;
-    if (b > 65536) b = 65536;
-    if (b < 1) b = 1;
-    return (unsigned)b;
-}
-
-// Dispatch a callable on the compile-time (Real, FORCE) of a domain.
-template <typename Fn>
-void dispatch(const lbm_domain* d, Fn&& fn) {
-    const bool f32 = d->p.prec == LBM_F32;
-    switch (d->p.force) {
-        case LBM_FORCE_SC:
-            if (f32) fn((float)0, std::integral_constant<int, lbm::FORCE_SC>());
-            else fn((double)0, std::integral_constant<int, lbm::FORCE_SC>());
-            break;
-        case LBM_FORCE_ZC:
-            if (f32) fn((float)0, std::integral_constant<int, lbm::FORCE_ZC>());
-            else fn((double)0, std::integral_constant<int, lbm::FORCE_ZC>());
-            break;
-        default:
-            if (f32) fn((float)0, std::integral_constant<int, lbm::FORCE_HYBRID>());
-            else fn((double)0, std::integral_constant<int, lbm::FORCE_HYBRID>());
-    }
-}
+namespace lbm_internal {
 
 lbm_status launch_phi(lbm_domain* d, int buf, hipStream_t s) {
     dispatch(d, [&](auto real, auto force) {
@@ -161,6 +97,10 @@ lbm_status launch_phi(lbm_domain* d, int buf, hipStream_t s) {
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
+
+}  // namespace lbm_internal
+
+namespace {
 
 template <typename Real, int FORCE, int TY>
 void launch_ref(lbm_domain* d, const lbm::StepArgs<Real>& a, hipStream_t s) {
@@ -392,6 +332,122 @@ lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream) {
     HIP_TRY(hipStreamSynchronize(stream));
     *ok = std::isfinite(h[0]) && std::isfinite(h[1]) && std::isfinite(h[2]) ? 1 : 0;
     return *ok ? LBM_OK : fail(LBM_ENONFINITE, "non-finite density after %lld steps", (long long)d->steps);
+}
+
+lbm_status lbm_state_bytes(const lbm_domain* d, size_t* bytes) {
+    if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    *bytes = d->off_f[1];
+    return LBM_OK;
+}
+
+lbm_status lbm_save_state(lbm_domain* d, void* state, hipStream_t stream) {
+    if (!d || !state) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(state, d->ws + d->off_f[d->cur], d->off_f[1], hipMemcpyDeviceToDevice, stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_domain* d, const void* state, hipStream_t stream) {
+    if (!d || !state) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(d->ws + d->off_f[d->cur], state, d->off_f[1], hipMemcpyDeviceToDevice, stream));
+    return launch_phi(d, d->cur, stream);
+}
+
+namespace {
+constexpr int ADJ_TY = 8;
+struct AdjLayout {
+    size_t plane, f, part, total;
+};
+AdjLayout adj_layout(const lbm_domain* d) {
+    AdjLayout L;
+    L.plane = align256((size_t)d->pitch * d->p.ny * sizeof(double));
+    L.f = d->off_f[1];
+    const size_t nb = (size_t)d->nxb * ((d->p.ny + ADJ_TY - 1) / ADJ_TY);
+    L.part = align256(nb * 2 * sizeof(double));
+    L.total = 5 * L.plane + L.part;
+    return L;
+}
+double alpha_prime(const lbm_domain* d) {
+    const double T = d->p.T;
+    if (d->p.eos == LBM_EOS_RK) return -0.5 / (T * std::sqrt(T));
+    if (d->p.eos == LBM_EOS_PR || d->p.eos == LBM_EOS_RKS) {
+        const double w = d->p.omega;
+        const double m = d->p.eos == LBM_EOS_PR ? 0.37464 + w * (1.54226 - 0.26992 * w) : 0.480 + w * (1.574 - 0.176 * w);
+        const double t = 1.0 + m * (1.0 - std::sqrt(T / d->Tc));
+        return -m * t / std::sqrt(T * d->Tc);
+    }
+    return 0.0;
+}
+}  // namespace
+
+lbm_status lbm_adjoint_workspace_bytes(const lbm_domain* d, size_t* bytes) {
+    if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    *bytes = adj_layout(d).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, double* grad,
+                            void* adj_ws, size_t adj_ws_bytes, hipStream_t stream) {
+    if (!d || !state_t || !lam_next || !lam_t || !grad || !adj_ws) return fail(LBM_EINVAL, "NULL argument");
+    if (lam_next == lam_t) return fail(LBM_EINVAL, "lam_next and lam_t must be distinct buffers");
+    if (d->p.prec != LBM_F64) return fail(LBM_EUNSUPPORTED, "the adjoint step is implemented for FP64 domains");
+    if (d->p.force == LBM_FORCE_HYBRID) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the SC and ZC forces");
+    if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+    AdjLayout L = adj_layout(d);
+    if (adj_ws_bytes < L.total) return fail(LBM_ENOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);
+    char* w = static_cast<char*>(adj_ws);
+    lbm::AdjArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.s = make_args<double>(d, d->cur, d->cur);
+    A.s.f_in = static_cast<const double*>(state_t);
+    double* phi = reinterpret_cast<double*>(w);
+    A.s.phi_in = phi;
+    A.s.phi_out = phi;
+    A.ax = reinterpret_cast<double*>(w + L.plane);
+    A.ay = reinterpret_cast<double*>(w + 2 * L.plane);
+    A.ubl = reinterpret_cast<double*>(w + 3 * L.plane);
+    A.rho = reinterpret_cast<double*>(w + 4 * L.plane);
+    A.partial = reinterpret_cast<double*>(w + 5 * L.plane);
+    A.lam_next = lam_next;
+    A.lam = lam_t;
+    A.e.kind = d->p.eos;
+    A.e.g = d->p.g;
+    A.e.b = d->p.b;
+    A.e.c_rep = d->p.k * d->p.R * d->p.T;
+    A.e.c_att = d->p.k * d->p.a * d->alpha;
+    A.e.c_attT = d->p.k * d->p.a * alpha_prime(d);
+    A.e.kR = d->p.k * d->p.R;
+    // potential field of state_t
+    {
+        lbm::StepArgs<double> pa = A.s;
+        pa.phi_out = phi;
+        if (d->p.force == LBM_FORCE_SC)
+            hipLaunchKernelGGL((lbm::k_phi<double, lbm::FORCE_SC>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, stream, pa);
+        else
+            hipLaunchKernelGGL((lbm::k_phi<double, lbm::FORCE_ZC>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, stream, pa);
+        HIP_TRY(hipGetLastError());
+    }
+    dim3 grid(d->nxb, (d->p.ny + ADJ_TY - 1) / ADJ_TY);
+    if (d->p.force == LBM_FORCE_SC) {
+        hipLaunchKernelGGL((lbm::k_adj_local<lbm::FORCE_SC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+        hipLaunchKernelGGL((lbm::k_adj_nonlocal<lbm::FORCE_SC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+    } else {
+        hipLaunchKernelGGL((lbm::k_adj_local<lbm::FORCE_ZC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+        hipLaunchKernelGGL((lbm::k_adj_nonlocal<lbm::FORCE_ZC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+    }
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(lbm::k_adj_accumulate, dim3(1), dim3(lbm::NT), 0, stream, A.partial, (long)grid.x * grid.y, grad);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_rho0(lbm_domain* d, const double* lam0, const double* ux0, const double* uy0, double* drho0,
+                            hipStream_t stream) {
+    if (!d || !lam0 || !drho0) return fail(LBM_EINVAL, "NULL argument");
+    const long n = (long)d->p.nx * d->p.ny;
+    hipLaunchKernelGGL(lbm::k_adj_rho0, dim3(grid_1d(n)), dim3(lbm::NT), 0, stream, lam0, (const double*)nullptr, ux0, uy0,
+                       n, drho0);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
 }
 
 void lbm_destroy(lbm_domain* d) { delete d; }

@@ -1,5 +1,13 @@
 // Device building blocks of the HDM pseudopotential lattice Boltzmann step on
 // gfx950: population layout, EOS potential, equilibrium, collision.
+//
+// Storage and arithmetic: populations are stored as `Real` (double or float),
+// the potential field always as double, and every arithmetic step is carried
+// out in double (values are widened on load and rounded once on store).  On
+// MI355X the FP64 vector rate equals the unpacked FP32 rate and the step is
+// bound by HBM bytes, so FP32 populations halve the dominant traffic without
+// FP32 arithmetic error; the potential field stays FP64 because its rounding
+// would enter the force through the stencil.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,9 +19,13 @@ namespace lbm {
 constexpr int Q = 9;
 constexpr int BX = 64;     // cells per x-block of the population layout (one wavefront)
 constexpr int JCAP = 40;   // capacity of the one-sided coefficient tables
+constexpr int KT = 4;      // largest number of outputs per thread of the blocked stencil
+constexpr int TAB_OFF = JCAP + KT - 1;   // table index of tap offset 0
+constexpr int TAB = 2 * TAB_OFF + 1;
 
-// Stencil radius kept per precision: the tail of the circulant row of Eq. 20
-// beyond it is below the unit roundoff (5e-17 in FP64, 3e-8 in FP32).
+// Stencil radius kept per population precision: the tail of the circulant row
+// of Eq. 20 beyond it is below the unit roundoff of the stored populations
+// (5e-17 in FP64, 3e-8 in FP32).
 template <typename Real> struct Radius;
 template <> struct Radius<double> { static constexpr int value = 39; };
 template <> struct Radius<float> { static constexpr int value = 18; };
@@ -39,26 +51,24 @@ __host__ __device__ inline size_t fidx(int x, int y, int q, int nxb) {
 
 // EOS potential U = g (k p_EOS(rho, T) - rho / 3) with the constants folded on
 // the host: c_rep = g k R T, c_att = g k a alpha(T), c_lin = g / 3.
-template <typename Real>
 struct DevEos {
     int kind;
-    Real c_rep, c_att, c_lin, b;
+    double c_rep, c_att, c_lin, b;
 };
 
-template <typename Real>
-__device__ inline Real potential(const DevEos<Real>& e, Real rho) {
-    Real rep, att;
+__device__ inline double potential(const DevEos& e, double rho) {
+    double rep, att;
     if (e.kind == EOS_CS) {  // Eq. 29, Carnahan-Starling repulsion
-        Real eta = e.b * rho * Real(0.25);
-        Real om = Real(1) - eta;
-        rep = rho * (Real(1) + eta * (Real(1) + eta * (Real(1) - eta))) / (om * om * om);
+        double eta = e.b * rho * 0.25;
+        double om = 1.0 - eta;
+        rep = rho * (1.0 + eta * (1.0 + eta * (1.0 - eta))) / (om * om * om);
         att = rho * rho;
     } else {  // Eqs. 24, 27, 28
-        rep = rho / (Real(1) - e.b * rho);
+        rep = rho / (1.0 - e.b * rho);
         if (e.kind == EOS_PR)
-            att = rho * rho / (Real(1) + e.b * rho * (Real(2) - e.b * rho));
+            att = rho * rho / (1.0 + e.b * rho * (2.0 - e.b * rho));
         else if (e.kind == EOS_RK || e.kind == EOS_RKS)
-            att = rho * rho / (Real(1) + e.b * rho);
+            att = rho * rho / (1.0 + e.b * rho);
         else
             att = rho * rho;
     }
@@ -67,40 +77,37 @@ __device__ inline Real potential(const DevEos<Real>& e, Real rho) {
 
 // The stored potential field: signed Phi = s sqrt|U| (Eq. 21) for the
 // Shan-Chen and hybrid forces, U itself for Zhang-Chen.
-template <typename Real, int FORCE>
-__device__ inline Real phi_of(Real U) {
+template <int FORCE>
+__device__ inline double phi_of(double U) {
     if (FORCE == FORCE_ZC) return U;
-    Real m = sqrt(fabs(U));
-    return U < Real(0) ? -m : m;
+    double m = sqrt(fabs(U));
+    return U < 0.0 ? -m : m;
 }
 
 // Equilibrium, Eq. 2: w_i rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2].
-template <typename Real>
-__device__ inline Real feq(int i, Real rho, Real ux, Real uy, Real usq) {
-    Real eu = Real(ex(i)) * ux + Real(ey(i)) * uy;
-    return wq<Real>(i) * rho * (Real(1) + Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq);
+__device__ inline double feq(int i, double rho, double ux, double uy, double usq) {
+    double eu = double(ex(i)) * ux + double(ey(i)) * uy;
+    return wq<double>(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
 }
 
 // BGK collision with Kupershtokh's exact-difference forcing (Eqs. 1, 10):
 //   f*_i = f_i - (f_i - f^eq_i(u)) / tau + f^eq_i(u + F/rho) - f^eq_i(u)
 //        = (1 - 1/tau) (f_i - f^eq_i(u)) + f^eq_i(u + F/rho),   u = j / rho.
-template <typename Real>
-__device__ inline void collide(Real (&f)[Q], Real rho, Real jx, Real jy, Real Fx, Real Fy, Real omega) {
-    Real ir = Real(1) / rho;
-    Real ux = jx * ir, uy = jy * ir;
-    Real vx = ux + Fx * ir, vy = uy + Fy * ir;
-    Real usq = ux * ux + uy * uy, vsq = vx * vx + vy * vy;
-    Real keep = Real(1) - omega;
+__device__ inline void collide(double (&f)[Q], double rho, double jx, double jy, double Fx, double Fy, double omega) {
+    double ir = 1.0 / rho;
+    double ux = jx * ir, uy = jy * ir;
+    double vx = ux + Fx * ir, vy = uy + Fy * ir;
+    double usq = ux * ux + uy * uy, vsq = vx * vx + vy * vy;
+    double keep = 1.0 - omega;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        Real e0 = feq(i, rho, ux, uy, usq);
-        Real e1 = feq(i, rho, vx, vy, vsq);
+        double e0 = feq(i, rho, ux, uy, usq);
+        double e1 = feq(i, rho, vx, vy, vsq);
         f[i] = keep * (f[i] - e0) + e1;
     }
 }
 
-template <typename Real>
-__device__ inline void moments(const Real (&f)[Q], Real& rho, Real& jx, Real& jy) {
+__device__ inline void moments(const double (&f)[Q], double& rho, double& jx, double& jy) {
     rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
     jy = (f[2] - f[4]) + ((f[5] - f[8]) + (f[6] - f[7]));
@@ -117,15 +124,19 @@ template <typename Real>
 struct StepArgs {
     const Real* __restrict__ f_in;
     Real* __restrict__ f_out;
-    const Real* __restrict__ phi_in;
-    Real* __restrict__ phi_out;
+    const double* __restrict__ phi_in;
+    double* __restrict__ phi_out;
     int nx, ny, nxb;  // lattice size, number of 64-cell x blocks
     int tx, ty;       // one-sided taps used along x and along y
-    Real omega;       // 1 / tau
-    Real A;           // hybrid weight (Eq. 9)
-    DevEos<Real> eos;
-    Real dx[JCAP];    // d_1 .. d_tx along x
-    Real dy[JCAP];    // d_1 .. d_ty along y
+    double omega;     // 1 / tau
+    double A;         // hybrid weight (Eq. 9)
+    DevEos eos;
+    double dx[JCAP];  // d_1 .. d_tx along x
+    double dy[JCAP];  // d_1 .. d_ty along y
+    // Sign-folded tables for the blocked stencil: tab[i] = c(i - TAB_OFF),
+    // c(n) = sign(n) d_|n| for 1 <= |n| <= taps, else 0.
+    double tx_tab[TAB];
+    double ty_tab[TAB];
 };
 
 }  // namespace lbm

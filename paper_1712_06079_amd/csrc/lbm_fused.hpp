@@ -24,69 +24,69 @@
 
 namespace lbm {
 
-template <typename Real, int TX, int TY, int K>
+template <typename Real, int TX, int TY, int K, int RX = Radius<Real>::value, int RY = Radius<Real>::value>
 struct FusedShape {
-    static constexpr int J = Radius<Real>::value;
     static constexpr int CW = TX + 2, CH = TY + 2;           // collision region
     static constexpr int NCELL = CW * CH;
     static constexpr int NSX = (CW + K - 1) / K;              // x segments per collision row
     static constexpr int NSY = (CH + K - 1) / K;              // y segments per collision column
-    static constexpr int RW = (NSX * K + 2 * J) | 1;          // row-bar pitch (odd: spreads LDS banks)
-    static constexpr int VH = NSY * K + 2 * J;                // column-bar height
-    static constexpr int PHI_WORDS = CH * RW + VH * CW;
-    static constexpr int FS_WORDS = Q * NCELL;
-    static constexpr int A_WORDS = PHI_WORDS > FS_WORDS ? PHI_WORDS : FS_WORDS;
-    static constexpr int WORDS = A_WORDS + 2 * NCELL;         // + Fx, Fy
+    static constexpr int RW = (NSX * K + 2 * RX) | 1;         // row-bar pitch (odd: spreads LDS banks)
+    static constexpr int VH = NSY * K + 2 * RY;               // column-bar height
+    static constexpr int PHI_DOUBLES = CH * RW + VH * CW;     // phi cross (double)
+    static constexpr int FS_DOUBLES = (Q * NCELL * (int)sizeof(Real) + 7) / 8;  // post-collision f (Real)
+    static constexpr int A_DOUBLES = PHI_DOUBLES > FS_DOUBLES ? PHI_DOUBLES : FS_DOUBLES;
+    static constexpr int DOUBLES = A_DOUBLES + 2 * NCELL;     // + Fx, Fy (double)
     static constexpr int NC = (NCELL + NT - 1) / NT;          // collision cells per thread
     static constexpr int NI = (TX * TY + NT - 1) / NT;        // interior cells per thread
     static constexpr int ITEMS_X = CH * NSX, ITEMS_Y = CW * NSY;
 };
 
-template <typename Real, int FORCE, int K>
-__device__ inline void stencil_window(const Real* __restrict__ base, int stride, const StepArgs<Real>& a, const Real* d,
-                                      Real (&acc)[K], Real (&accu)[K]) {
-    constexpr int J = Radius<Real>::value;
+// K outputs of the explicit Eq. 20 stencil of radius R along one line from one
+// window: output k sits at window position R + k; every window value is loaded
+// once from LDS and added to the K outputs with the coefficients c(m - R - k),
+// which are K consecutive entries of the sign-folded table (one scalar load).
+template <int FORCE, int K, int R>
+__device__ inline void stencil_window(const double* __restrict__ base, int stride, const double* __restrict__ tab,
+                                      double (&acc)[K], double (&accu)[K]) {
+    static_assert(R + K - 1 <= TAB_OFF && K <= KT, "stencil window outside the coefficient table");
 #pragma unroll
-    for (int k = 0; k < K; ++k) { acc[k] = Real(0); accu[k] = Real(0); }
-#pragma unroll
-    for (int m = 0; m < 2 * J + K; ++m) {
-        const Real v = base[m * stride];
-        const Real vo = (FORCE == FORCE_ZC) ? v : fabs(v);
+    for (int k = 0; k < K; ++k) { acc[k] = 0.0; accu[k] = 0.0; }
+#pragma unroll 4
+    for (int m = 0; m < 2 * R + K; ++m) {
+        const double v = base[m * stride];
+        const double vo = (FORCE == FORCE_ZC) ? v : fabs(v);
+        const double vu = v * fabs(v);
+        const double* t = tab + (TAB_OFF - R - (K - 1)) + m;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int n = m - k - J;  // tap offset of this value from output k
-            if (n != 0 && n >= -J && n <= J) {
-                const Real c = n > 0 ? d[n - 1] : -d[-n - 1];
-                acc[k] += c * vo;
-                if (FORCE == FORCE_HYBRID) accu[k] += c * (v * fabs(v));
-            }
+            const double c = t[K - 1 - k];
+            acc[k] += c * vo;
+            if (FORCE == FORCE_HYBRID) accu[k] += c * vu;
         }
     }
 }
 
-template <typename Real, int FORCE>
-__device__ inline void force_from(Real phic, Real g, Real gu, Real A, Real& F) {
-    if (FORCE == FORCE_ZC) {
-        F = -g;
-    } else {
-        F = Real(-2) * phic * g;
-        if (FORCE == FORCE_HYBRID) F = A * (-gu) + (Real(1) - Real(2) * A) * F;
-    }
+template <int FORCE>
+__device__ inline double force_from(double phic, double g, double gu, double A) {
+    if (FORCE == FORCE_ZC) return -g;
+    const double F = -2.0 * phic * g;
+    return FORCE == FORCE_HYBRID ? A * (-gu) + (1.0 - 2.0 * A) * F : F;
 }
 
-template <typename Real, int FORCE, int TX, int TY, int K>
-__global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
-    using S = FusedShape<Real, TX, TY, K>;
-    constexpr int J = S::J, CW = S::CW, CH = S::CH;
-    __shared__ Real sm[S::WORDS];
-    Real* rowr = sm;                   // [CH][RW]   phi rows  x0-1-J .. x0+TX+J (+ segment padding)
-    Real* colr = sm + CH * S::RW;      // [VH][CW]   phi cols  y0-1-J .. y0+TY+J (+ segment padding)
-    Real* fst = sm;                    // [Q][CH][CW] post-collision populations (after phase 2)
-    Real* Fx = sm + S::A_WORDS;        // [CH][CW]
-    Real* Fy = Fx + S::NCELL;
+// One TX x TY tile with origin (x0, y0) of the domain described by `a`;
+// `sm` is the workgroup's LDS of FusedShape::DOUBLES doubles.  RX and RY are the
+// stencil radii staged along x and y (>= the domain's taps along each axis).
+template <typename Real, int FORCE, int TX, int TY, int K, int RX, int RY>
+__device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, double* sm) {
+    using S = FusedShape<Real, TX, TY, K, RX, RY>;
+    constexpr int CW = S::CW, CH = S::CH;
+    double* rowr = sm;                          // [CH][RW]   phi rows  x0-1-RX .. x0+TX+RX (+ segment padding)
+    double* colr = rowr + CH * S::RW;           // [VH][CW]   phi cols  y0-1-RY .. y0+TY+RY (+ segment padding)
+    Real* fst = reinterpret_cast<Real*>(sm);    // [Q][CH][CW] post-collision populations (after phase 2)
+    double* Fx = sm + S::A_DOUBLES;             // [CH][CW]
+    double* Fy = Fx + S::NCELL;
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
 
     // Phase 0: loads of f_t for this thread's collision cells.
@@ -105,45 +105,35 @@ __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
     // Phase 1: phi cross.
     for (int i = tid; i < CH * S::RW; i += NT) {
         const int r = i / S::RW, c = i - r * S::RW;
-        const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - J + c, nx);
+        const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
         rowr[i] = a.phi_in[(long)yw * pitch + xw];
     }
     for (int i = tid; i < S::VH * CW; i += NT) {
         const int r = i / CW, c = i - r * CW;
-        const int yw = wrap(y0 - 1 - J + r, ny), xw = wrap(x0 - 1 + c, nx);
+        const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
         colr[i] = a.phi_in[(long)yw * pitch + xw];
     }
     __syncthreads();
 
     // Phase 2: gradients and force.
     for (int it = tid; it < S::ITEMS_X + S::ITEMS_Y; it += NT) {
-        Real acc[K], accu[K];
+        double acc[K], accu[K];
         if (it < S::ITEMS_X) {
             const int cy = it % CH, s = it / CH;  // consecutive lanes: consecutive rows
-            const Real* base = rowr + cy * S::RW + s * K;
-            stencil_window<Real, FORCE, K>(base, 1, a, a.dx, acc, accu);
+            stencil_window<FORCE, K, RX>(rowr + cy * S::RW + s * K, 1, a.tx_tab, acc, accu);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int cx = s * K + k;
-                if (cx < CW) {
-                    Real F;
-                    force_from<Real, FORCE>(rowr[cy * S::RW + cx + J], acc[k], accu[k], a.A, F);
-                    Fx[cy * CW + cx] = F;
-                }
+                if (cx < CW) Fx[cy * CW + cx] = force_from<FORCE>(rowr[cy * S::RW + cx + RX], acc[k], accu[k], a.A);
             }
         } else {
             const int jt = it - S::ITEMS_X;
             const int cx = jt % CW, s = jt / CW;  // consecutive lanes: consecutive columns
-            const Real* base = colr + (s * K) * CW + cx;
-            stencil_window<Real, FORCE, K>(base, CW, a, a.dy, acc, accu);
+            stencil_window<FORCE, K, RY>(colr + (s * K) * CW + cx, CW, a.ty_tab, acc, accu);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int cy = s * K + k;
-                if (cy < CH) {
-                    Real F;
-                    force_from<Real, FORCE>(colr[(cy + J) * CW + cx], acc[k], accu[k], a.A, F);
-                    Fy[cy * CW + cx] = F;
-                }
+                if (cy < CH) Fy[cy * CW + cx] = force_from<FORCE>(colr[(cy + RY) * CW + cx], acc[k], accu[k], a.A);
             }
         }
     }
@@ -154,11 +144,14 @@ __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
     for (int i = 0; i < S::NC; ++i) {
         const int c = tid + i * NT;
         if (c < S::NCELL) {
-            Real rho, jx, jy;
-            moments(f[i], rho, jx, jy);
-            collide(f[i], rho, jx, jy, Fx[c], Fy[c], a.omega);
+            double g[Q];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) fst[q * S::NCELL + c] = f[i][q];
+            for (int q = 0; q < Q; ++q) g[q] = (double)f[i][q];
+            double rho, jx, jy;
+            moments(g, rho, jx, jy);
+            collide(g, rho, jx, jy, Fx[c], Fy[c], a.omega);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fst[q * S::NCELL + c] = (Real)g[q];
         }
     }
     __syncthreads();
@@ -171,18 +164,75 @@ __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
             const int ly = c / TX, lx = c - ly * TX;
             const int x = x0 + lx, y = y0 + ly;
             if (x < nx && y < ny) {
-                Real g[Q];
+                double g[Q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    g[q] = fst[q * S::NCELL + (ly + 1 - ey(q)) * CW + (lx + 1 - ex(q))];
-                    a.f_out[fidx(x, y, q, nxb)] = g[q];
+                    const Real v = fst[q * S::NCELL + (ly + 1 - ey(q)) * CW + (lx + 1 - ex(q))];
+                    a.f_out[fidx(x, y, q, nxb)] = v;
+                    g[q] = (double)v;
                 }
-                Real rho, jx, jy;
+                double rho, jx, jy;
                 moments(g, rho, jx, jy);
-                a.phi_out[(long)y * pitch + x] = phi_of<Real, FORCE>(potential(a.eos, rho));
+                a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, rho));
             }
         }
     }
+}
+
+template <typename Real, int FORCE, int TX, int TY, int K>
+__global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
+    constexpr int R = Radius<Real>::value;
+    __shared__ double sm[FusedShape<Real, TX, TY, K, R, R>::DOUBLES];
+    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, blockIdx.x * TX, blockIdx.y * TY, sm);
+}
+
+// Batched step: one launch advances every domain of a batch by one step.
+// `tiles` lists (domain, x0, y0) work items in the scheduler's order; workgroup
+// b processes items b, b + gridDim.x, ... (a persistent loop when the grid is
+// smaller than the list).  `descs` holds one StepArgs per domain for this
+// step's buffer parity.  Every item runs the same tile code as the
+// single-domain kernel.
+struct BatchTile {
+    int d, x0, y0, pad;
+};
+
+template <typename Real, int FORCE, int TY, int RY>
+__global__ void __launch_bounds__(NT) k_batch(const StepArgs<Real>* __restrict__ descs,
+                                              const BatchTile* __restrict__ tiles, int ntiles) {
+    constexpr int RX = Radius<Real>::value;
+    __shared__ double sm[FusedShape<Real, BX, TY, 4, RX, RY>::DOUBLES];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile w = tiles[t];
+        fused_tile<Real, FORCE, BX, TY, 4, RX, RY>(descs[w.d], w.x0, w.y0, sm);
+        __syncthreads();
+    }
+}
+
+// Per-domain non-finite flags of a batch: flags[d] |= 1 if any density of a
+// tile of domain d is not finite (flags cleared by the caller beforehand).
+template <typename Real>
+__global__ void __launch_bounds__(NT) k_batch_finite(const StepArgs<Real>* __restrict__ descs,
+                                                     const BatchTile* __restrict__ tiles, int ntiles, int ty,
+                                                     int* __restrict__ flags) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const BatchTile w = tiles[t];
+        const StepArgs<Real>& a = descs[w.d];
+        int bad = 0;
+        for (int c = threadIdx.x; c < BX * ty; c += NT) {
+            const int x = w.x0 + (c & (BX - 1)), y = w.y0 + c / BX;
+            if (x < a.nx && y < a.ny) {
+                double r = 0.0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) r += (double)a.f_in[fidx(x, y, q, a.nxb)];
+                if (!isfinite(r)) bad = 1;
+            }
+        }
+        if (bad) atomicOr(&flags[w.d], 1);
+    }
+}
+
+static __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 template <typename Real, int FORCE, int TX, int TY, int K>
@@ -191,8 +241,8 @@ inline void launch_fused_t(const StepArgs<Real>& a, hipStream_t s) {
     hipLaunchKernelGGL((k_fused<Real, FORCE, TX, TY, K>), grid, dim3(NT), 0, s, a);
 }
 
-// Tile choice: FP64 uses 64 x 8 tiles (two workgroups per CU fit in LDS),
-// FP32 64 x 16; tile_y selects another instantiation (0 = default).
+// Tile choice: FP64 storage uses 64 x 8 tiles (two workgroups per CU fit in
+// LDS), FP32 storage 64 x 16; tile_y selects another instantiation (0 = default).
 template <typename Real, int FORCE>
 inline bool launch_fused(const StepArgs<Real>& a, int tile_y, hipStream_t s) {
     const int ty = tile_y ? tile_y : (sizeof(Real) == 8 ? 8 : 16);

@@ -27,22 +27,23 @@ __global__ void __launch_bounds__(NT) k_init(StepArgs<Real> a, const double* __r
         Real* f = a.f_out;
         if (x < a.nx) {
             long s = (long)y * a.nx + x;
-            Real rho = (Real)rho0[s];
-            Real ux = ux0 ? (Real)ux0[s] : Real(0), uy = uy0 ? (Real)uy0[s] : Real(0);
-            Real usq = ux * ux + uy * uy;
-            Real fi[Q];
+            double rho = rho0[s];
+            double ux = ux0 ? ux0[s] : 0.0, uy = uy0 ? uy0[s] : 0.0;
+            double usq = ux * ux + uy * uy;
+            double fi[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                fi[i] = feq(i, rho, ux, uy, usq);
-                f[fidx(x, y, i, a.nxb)] = fi[i];
+                const Real v = (Real)feq(i, rho, ux, uy, usq);
+                f[fidx(x, y, i, a.nxb)] = v;
+                fi[i] = (double)v;  // the stored value defines the state
             }
-            Real r, jx, jy;
+            double r, jx, jy;
             moments(fi, r, jx, jy);
-            a.phi_out[(long)y * pitch + x] = phi_of<Real, FORCE>(potential(a.eos, r));
+            a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, r));
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[fidx(x, y, i, a.nxb)] = Real(0);
-            a.phi_out[(long)y * pitch + x] = Real(0);
+            a.phi_out[(long)y * pitch + x] = 0.0;
         }
     }
 }
@@ -54,12 +55,12 @@ __global__ void __launch_bounds__(NT) k_phi(StepArgs<Real> a) {
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < total; c += (long)gridDim.x * NT) {
         int y = (int)(c / pitch), x = (int)(c - (long)y * pitch);
         if (x >= a.nx) continue;
-        Real fi[Q];
+        double fi[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) fi[i] = a.f_in[fidx(x, y, i, a.nxb)];
-        Real r, jx, jy;
+        for (int i = 0; i < Q; ++i) fi[i] = (double)a.f_in[fidx(x, y, i, a.nxb)];
+        double r, jx, jy;
         moments(fi, r, jx, jy);
-        a.phi_out[(long)y * pitch + x] = phi_of<Real, FORCE>(potential(a.eos, r));
+        a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, r));
     }
 }
 
@@ -73,12 +74,12 @@ struct Cross {
     static constexpr int J = Radius<Real>::value;
     static constexpr int RW = BX + 2 * J;
     static constexpr int CH = TY + 2 * J;
-    Real row[TY][RW];
-    Real col[CH][BX];
+    double row[TY][RW];
+    double col[CH][BX];
 };
 
 template <typename Real, int TY>
-__device__ inline void stage_cross(Cross<Real, TY>& s, const Real* __restrict__ phi, int x0, int y0, int nx,
+__device__ inline void stage_cross(Cross<Real, TY>& s, const double* __restrict__ phi, int x0, int y0, int nx,
                                    int ny, int pitch) {
     using C = Cross<Real, TY>;
     for (int i = threadIdx.x; i < TY * C::RW; i += NT) {
@@ -95,41 +96,37 @@ __device__ inline void stage_cross(Cross<Real, TY>& s, const Real* __restrict__ 
     }
 }
 
-// Stencil operands: Phi = |phi| (Shan-Chen), U (Zhang-Chen), U = phi |phi| (hybrid's ZC part).
-template <typename Real> __device__ inline Real op_abs(Real v) { return fabs(v); }
-template <typename Real> __device__ inline Real op_sq(Real v) { return v * fabs(v); }
-
-// Interaction force at tile cell (r, lx) from the staged cross:
+// Interaction force at tile cell (r, lx) from the staged cross (double arithmetic):
 //  SC (Eq. 22): F = -2 s Phi D Phi = -2 phi(x) D|phi|
 //  ZC (Eq. 7):  F = -D U
 //  hybrid (Eq. 9): A F^ZC + (1 - 2A) F^SC with U = phi |phi|.
 template <typename Real, int FORCE, int TY>
-__device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& a, int r, int lx, Real& Fx, Real& Fy) {
+__device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& a, int r, int lx, double& Fx, double& Fy) {
     constexpr int J = Cross<Real, TY>::J;
-    const Real pc = s.row[r][J + lx];
+    const double pc = s.row[r][J + lx];
     if (FORCE == FORCE_ZC) {
-        Real gx = 0, gy = 0;
+        double gx = 0, gy = 0;
         for (int j = 1; j <= a.tx; ++j) gx += a.dx[j - 1] * (s.row[r][J + lx + j] - s.row[r][J + lx - j]);
         for (int j = 1; j <= a.ty; ++j) gy += a.dy[j - 1] * (s.col[J + r + j][lx] - s.col[J + r - j][lx]);
         Fx = -gx;
         Fy = -gy;
     } else {
-        Real gx = 0, gy = 0, ux = 0, uy = 0;
+        double gx = 0, gy = 0, ux = 0, uy = 0;
         for (int j = 1; j <= a.tx; ++j) {
-            Real p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
-            gx += a.dx[j - 1] * (op_abs(p) - op_abs(m));
-            if (FORCE == FORCE_HYBRID) ux += a.dx[j - 1] * (op_sq(p) - op_sq(m));
+            const double p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
+            gx += a.dx[j - 1] * (fabs(p) - fabs(m));
+            if (FORCE == FORCE_HYBRID) ux += a.dx[j - 1] * (p * fabs(p) - m * fabs(m));
         }
         for (int j = 1; j <= a.ty; ++j) {
-            Real p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
-            gy += a.dy[j - 1] * (op_abs(p) - op_abs(m));
-            if (FORCE == FORCE_HYBRID) uy += a.dy[j - 1] * (op_sq(p) - op_sq(m));
+            const double p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
+            gy += a.dy[j - 1] * (fabs(p) - fabs(m));
+            if (FORCE == FORCE_HYBRID) uy += a.dy[j - 1] * (p * fabs(p) - m * fabs(m));
         }
-        Fx = Real(-2) * pc * gx;
-        Fy = Real(-2) * pc * gy;
+        Fx = -2.0 * pc * gx;
+        Fy = -2.0 * pc * gy;
         if (FORCE == FORCE_HYBRID) {
-            Fx = a.A * (-ux) + (Real(1) - Real(2) * a.A) * Fx;
-            Fy = a.A * (-uy) + (Real(1) - Real(2) * a.A) * Fy;
+            Fx = a.A * (-ux) + (1.0 - 2.0 * a.A) * Fx;
+            Fy = a.A * (-uy) + (1.0 - 2.0 * a.A) * Fy;
         }
     }
 }
@@ -148,13 +145,13 @@ __global__ void __launch_bounds__(NT) k_collide(StepArgs<Real> a) {
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
         const int y = y0 + r;
         if (y >= a.ny) break;
-        Real Fx, Fy;
+        double Fx, Fy;
         force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
         if (x >= a.nx) continue;
-        Real f[Q];
+        double f[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
-        Real rho, jx, jy;
+        for (int i = 0; i < Q; ++i) f[i] = (double)a.f_in[fidx(x, y, i, a.nxb)];
+        double rho, jx, jy;
         moments(f, rho, jx, jy);
         collide(f, rho, jx, jy, Fx, Fy, a.omega);
 #pragma unroll
@@ -162,7 +159,7 @@ __global__ void __launch_bounds__(NT) k_collide(StepArgs<Real> a) {
             int xd = x + ex(i), yd = y + ey(i);
             xd = xd < 0 ? a.nx - 1 : (xd >= a.nx ? 0 : xd);
             yd = yd < 0 ? a.ny - 1 : (yd >= a.ny ? 0 : yd);
-            a.f_out[fidx(xd, yd, i, a.nxb)] = f[i];
+            a.f_out[fidx(xd, yd, i, a.nxb)] = (Real)f[i];
         }
     }
 }
@@ -197,22 +194,22 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
         const int y = y0 + r;
         if (y >= a.ny) break;
-        Real Fx, Fy;
+        double Fx, Fy;
         force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
         if (x >= a.nx) continue;
-        Real f[Q];
+        double f[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
-        Real rho, jx, jy;
+        for (int i = 0; i < Q; ++i) f[i] = (double)a.f_in[fidx(x, y, i, a.nxb)];
+        double rho, jx, jy;
         moments(f, rho, jx, jy);
         double dr = rho;
-        double vx = ((double)jx + 0.5 * (double)Fx) / dr;
-        double vy = ((double)jy + 0.5 * (double)Fy) / dr;
+        double vx = (jx + 0.5 * Fx) / dr;
+        double vy = (jy + 0.5 * Fy) / dr;
         long o = (long)y * a.nx + x;
         if (rho_o) rho_o[o] = dr;
         if (ux_o) ux_o[o] = vx;
         if (uy_o) uy_o[o] = vy;
-        if (p_o) p_o[o] = dr / 3.0 + (double)potential(a.eos, rho);
+        if (p_o) p_o[o] = dr / 3.0 + potential(a.eos, rho);
         m += dr;
         px += dr * vx;
         py += dr * vy;
@@ -242,7 +239,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
 
 // One workgroup: thread t sums partials t, t + 256, ... in order, then a fixed
 // butterfly and the four wavefronts in index order.
-__global__ void __launch_bounds__(NT) k_totals(const double* __restrict__ partial, long nblocks, double* __restrict__ out) {
+static __global__ void __launch_bounds__(NT) k_totals(const double* __restrict__ partial, long nblocks, double* __restrict__ out) {
     __shared__ double red[4][NT / BX];
     double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     for (long b = threadIdx.x; b < nblocks; b += NT) {
@@ -283,7 +280,7 @@ __global__ void __launch_bounds__(NT) k_set_f(StepArgs<Real> a, const double* __
 
 // Validation of an initial density: flag[0] = 1 if any rho0 is non-finite,
 // <= 0 or at / beyond the pole of the repulsive term.
-__global__ void __launch_bounds__(NT) k_check_rho0(const double* __restrict__ rho0, long n, double rho_max,
+static __global__ void __launch_bounds__(NT) k_check_rho0(const double* __restrict__ rho0, long n, double rho_max,
                                                    int* __restrict__ flag) {
     int bad = 0;
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
