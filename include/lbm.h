@@ -65,7 +65,8 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
  *          alpha = 1/sqrt(T)), RKS (Eq. 27 with the Soave alpha(T_r))
  *  force   Shan-Chen (Eq. 22), Zhang-Chen (Eq. 7), hybrid (Eq. 9, weight A)
  *  grad    HDM (Eq. 20) or central difference (Eq. 14)
- *  prec    storage and arithmetic precision of populations and Phi
+ *  prec    storage precision of the populations (FP64 or FP32); the potential
+ *          field and all arithmetic are FP64 in both cases
  *  tau     relaxation time (Eq. 1), > 1/2
  *  a,b,R   EOS constants; omega is the acentric factor (PR, RKS)
  *  T       absolute temperature (T_r = T / Tc; see lbm_critical)
@@ -99,7 +100,7 @@ lbm_status lbm_maxwell(const lbm_params* p, double T, double* rho_v, double* rho
 /* Explicit circulant row of the periodic compact difference (Sec. 3.2 Eq. 20)
  * on n >= 5 points, as the kernels use it (host, synchronous): d[0..*taps-1]
  * receive d_1..d_taps with (D u)_i = sum_j d_j (u_{i+j} - u_{i-j}); taps =
- * min(radius, (n-1)/2) with radius 39 for LBM_F64 and 18 for LBM_F32.  d must
+ * min(radius, (n-1)/2) with radius 39 for LBM_F64 and 28 for LBM_F32.  d must
  * hold 40 doubles. */
 lbm_status lbm_hdm_row(int32_t n, int32_t prec, double* d, int32_t* taps);
 

@@ -11,7 +11,7 @@
 // and d_j = sum_m g_{(j - m) mod N} b_m with b_{+-1} = +-7/9, b_{+-2} = +-1/36.
 // |d_j| decays like |r|^j (|r| = 0.382), so the stencil may be cut at the
 // radius where the tail drops below the working precision: 39 in FP64
-// (tail 5e-17 of d_1), 18 in FP32 (3e-8).  For N <= 2J + 1 the whole
+// (tail 5e-17 of d_1), 28 with FP32 populations (4e-12).  For N <= 2J + 1 the whole
 // periodic row is used and the result is the exact periodic solve.
 #include "hdm_coeffs.hpp"
 
@@ -42,6 +42,24 @@ void hdm_row(int n, int taps, double* d) {
         for (int k = 0; k < 4; ++k) s += g(j - bo[k]) * bv[k];
         d[j - 1] = (double)s;
     }
+}
+
+// Infinite-line row: with g_n = (3/sqrt 5) r^|n|, d_j = sum_m g_{j-m} b_m.  For
+// j >= 3 every offset j - m is positive, so d_j = C r^j with
+// C = (3/sqrt 5) [(7/9)(1/r - r) + (1/36)(1/r^2 - r^2)]; d_1 and d_2 keep the
+// terms where |j - m| folds.
+void hdm_infinite(double* r_out, double* d1, double* d2, double* C) {
+    typedef long double LD;
+    const LD s5 = std::sqrt((LD)5.0);
+    const LD r = (s5 - (LD)3.0) / (LD)2.0;
+    const LD c = (LD)3.0 / s5;
+    const LD b1 = (LD)7.0 / (LD)9.0, b2 = (LD)1.0 / (LD)36.0;
+    auto g = [&](int n) { return c * std::pow(r, (LD)(n < 0 ? -n : n)); };
+    auto d = [&](int j) { return b1 * (g(j - 1) - g(j + 1)) + b2 * (g(j - 2) - g(j + 2)); };
+    *r_out = (double)r;
+    *d1 = (double)d(1);
+    *d2 = (double)d(2);
+    *C = (double)(c * (b1 * ((LD)1.0 / r - r) + b2 * ((LD)1.0 / (r * r) - r * r)));
 }
 
 // Central difference, Eq. 14 (h = 1): d_1 = 1/2.

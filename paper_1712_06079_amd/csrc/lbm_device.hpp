@@ -23,12 +23,15 @@ constexpr int KT = 4;      // largest number of outputs per thread of the blocke
 constexpr int TAB_OFF = JCAP + KT - 1;   // table index of tap offset 0
 constexpr int TAB = 2 * TAB_OFF + 1;
 
-// Stencil radius kept per population precision: the tail of the circulant row
-// of Eq. 20 beyond it is below the unit roundoff of the stored populations
-// (5e-17 in FP64, 3e-8 in FP32).
+// Stencil radius kept per population precision.  FP64: the tail of the
+// circulant row of Eq. 20 beyond 39 taps is 5e-17 of d_1, below rounding.
+// FP32 populations: 28 taps (tail 4e-12).  A tail at the FP32 unit roundoff
+// (18 taps, 3e-8) is not enough: over 2000 steps of the 64^2 slab it moves the
+// densities by 6e-5, while 28 taps move them by 1e-9, far below the 1e-6 the
+// FP32 population rounding itself causes.
 template <typename Real> struct Radius;
 template <> struct Radius<double> { static constexpr int value = 39; };
-template <> struct Radius<float> { static constexpr int value = 18; };
+template <> struct Radius<float> { static constexpr int value = 28; };
 
 enum { FORCE_SC = 0, FORCE_ZC = 1, FORCE_HYBRID = 2 };
 enum { EOS_VDW = 0, EOS_PR = 1, EOS_CS = 2, EOS_RK = 3, EOS_RKS = 4 };
@@ -113,9 +116,14 @@ __device__ inline void moments(const double (&f)[Q], double& rho, double& jx, do
     jy = (f[2] - f[4]) + ((f[5] - f[8]) + (f[6] - f[7]));
 }
 
+// v mod n for the offsets the kernels wrap (a tile origin plus a stencil
+// radius and a ring cell): they lie within a few periods of [0, n), so
+// conditional corrections replace an integer division (which has no hardware
+// instruction).  Large lattices need at most one correction.
 __device__ inline int wrap(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
 }
 
 // Kernel arguments of one domain step (passed by value; the coefficient
@@ -137,6 +145,11 @@ struct StepArgs {
     // c(n) = sign(n) d_|n| for 1 <= |n| <= taps, else 0.
     double tx_tab[TAB];
     double ty_tab[TAB];
+    // Geometric form of the infinite-line row (d_j = C r^j for j >= 3), used
+    // along an axis whose length exceeds 2R + 1 (there the periodic row equals
+    // it to rounding): rec_x / rec_y select it per axis.
+    int rec_x, rec_y;
+    double rr, rr3, rd1, rd2, rC;
 };
 
 }  // namespace lbm

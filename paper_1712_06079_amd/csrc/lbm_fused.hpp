@@ -28,10 +28,14 @@ template <typename Real, int TX, int TY, int K, int RX = Radius<Real>::value, in
 struct FusedShape {
     static constexpr int CW = TX + 2, CH = TY + 2;           // collision region
     static constexpr int NCELL = CW * CH;
-    static constexpr int NSX = (CW + K - 1) / K;              // x segments per collision row
-    static constexpr int NSY = (CH + K - 1) / K;              // y segments per collision column
-    static constexpr int RW = (NSX * K + 2 * RX) | 1;         // row-bar pitch (odd: spreads LDS banks)
-    static constexpr int VH = NSY * K + 2 * RY;               // column-bar height
+    static constexpr int NSX = (CW + K - 1) / K;              // x segments per collision row (explicit form)
+    static constexpr int NSY = (CH + K - 1) / K;              // y segments per collision column (explicit form)
+    static constexpr int NSEGX = 4;                           // x segments per collision row (recursive form)
+    static constexpr int SX = (CW + NSEGX - 1) / NSEGX;       // outputs per recursive x segment
+    static constexpr int XSPAN = NSX * K > NSEGX * SX ? NSX * K : NSEGX * SX;
+    static constexpr int RW = (XSPAN + 2 * RX) | 1;           // row-bar pitch (odd: spreads LDS banks)
+    static constexpr int VH = NSY * K + 2 * RY;               // column-bar height (>= CH + 2 RY)
+    static constexpr int RITEMS_X = CH * NSEGX, RITEMS_Y = CW;
     static constexpr int PHI_DOUBLES = CH * RW + VH * CW;     // phi cross (double)
     static constexpr int FS_DOUBLES = (Q * NCELL * (int)sizeof(Real) + 7) / 8;  // post-collision f (Real)
     static constexpr int A_DOUBLES = PHI_DOUBLES > FS_DOUBLES ? PHI_DOUBLES : FS_DOUBLES;
@@ -62,6 +66,49 @@ __device__ inline void stencil_window(const double* __restrict__ base, int strid
             const double c = t[K - 1 - k];
             acc[k] += c * vo;
             if (FORCE == FORCE_HYBRID) accu[k] += c * vu;
+        }
+    }
+}
+
+// S outputs of Eq. 20 along one line of length > 2R + 1 in geometric form:
+// sum_j d_j (u_{i+j} - u_{i-j}) = d_1 (u_{i+1} - u_{i-1}) + d_2 (u_{i+2} - u_{i-2})
+// + C (P_i - M_i), P_i = sum_{j>=3} r^j u_{i+j}, M_i = sum_{j>=3} r^j u_{i-j},
+// evaluated by P_{i-1} = r P_i + r^3 u_{i+2} (right to left) and
+// M_{i+1} = r M_i + r^3 u_{i-2} (left to right), each started R - 2 cells
+// beyond the segment so that every output gets at least the taps j <= R.
+// base[k * stride] is the operand's window value at output k (k in [-R, S-1+R]).
+template <int FORCE, int S, int R>
+__device__ inline void stencil_recursive(const double* __restrict__ base, int stride, double r, double r3, double d1,
+                                         double d2, double C, double (&out)[S], double (&outu)[S]) {
+    static_assert(R >= 3, "geometric form needs R >= 3");
+    double M[S], Mu[S];
+    double m = 0.0, mu = 0.0;
+#pragma unroll
+    for (int i = -(R - 2); i < S - 1; ++i) {
+        const double v = base[(i - 2) * stride];
+        m = fma(r, m, r3 * (FORCE == FORCE_ZC ? v : fabs(v)));
+        if (FORCE == FORCE_HYBRID) mu = fma(r, mu, r3 * (v * fabs(v)));
+        if (i + 1 >= 0) {
+            M[i + 1] = m;
+            Mu[i + 1] = mu;
+        }
+    }
+    double p = 0.0, pu = 0.0;
+#pragma unroll
+    for (int i = S - 1 + (R - 2); i >= 1; --i) {
+        const double v = base[(i + 2) * stride];
+        p = fma(r, p, r3 * (FORCE == FORCE_ZC ? v : fabs(v)));
+        if (FORCE == FORCE_HYBRID) pu = fma(r, pu, r3 * (v * fabs(v)));
+        const int o = i - 1;
+        if (o < S) {
+            const double a1 = base[(o + 1) * stride], b1 = base[(o - 1) * stride];
+            const double a2 = base[(o + 2) * stride], b2 = base[(o - 2) * stride];
+            if (FORCE == FORCE_ZC)
+                out[o] = d1 * (a1 - b1) + d2 * (a2 - b2) + C * (p - M[o]);
+            else
+                out[o] = d1 * (fabs(a1) - fabs(b1)) + d2 * (fabs(a2) - fabs(b2)) + C * (p - M[o]);
+            if (FORCE == FORCE_HYBRID)
+                outu[o] = d1 * (a1 * fabs(a1) - b1 * fabs(b1)) + d2 * (a2 * fabs(a2) - b2 * fabs(b2)) + C * (pu - Mu[o]);
         }
     }
 }
@@ -115,10 +162,34 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     }
     __syncthreads();
 
-    // Phase 2: gradients and force.
-    for (int it = tid; it < S::ITEMS_X + S::ITEMS_Y; it += NT) {
+    // Phase 2: gradients and force.  Axes longer than 2R + 1 use the geometric
+    // recursion (one segment of SX outputs per x item, a whole collision
+    // column per y item); shorter axes the explicit K-blocked window.
+    const int nix = a.rec_x ? S::RITEMS_X : S::ITEMS_X;
+    const int niy = a.rec_y ? S::RITEMS_Y : S::ITEMS_Y;
+    for (int it = tid; it < nix + niy; it += NT) {
+        if (it < nix && a.rec_x) {
+            const int cy = it % CH, s = it / CH;
+            double out[S::SX], outu[S::SX];
+            stencil_recursive<FORCE, S::SX, RX>(rowr + cy * S::RW + RX + s * S::SX, 1, a.rr, a.rr3, a.rd1, a.rd2, a.rC,
+                                                out, outu);
+#pragma unroll
+            for (int k = 0; k < S::SX; ++k) {
+                const int cx = s * S::SX + k;
+                if (cx < CW) Fx[cy * CW + cx] = force_from<FORCE>(rowr[cy * S::RW + cx + RX], out[k], outu[k], a.A);
+            }
+            continue;
+        }
+        if (it >= nix && a.rec_y) {
+            const int cx = it - nix;
+            double out[CH], outu[CH];
+            stencil_recursive<FORCE, CH, RY>(colr + RY * CW + cx, CW, a.rr, a.rr3, a.rd1, a.rd2, a.rC, out, outu);
+#pragma unroll
+            for (int k = 0; k < CH; ++k) Fy[k * CW + cx] = force_from<FORCE>(colr[(k + RY) * CW + cx], out[k], outu[k], a.A);
+            continue;
+        }
         double acc[K], accu[K];
-        if (it < S::ITEMS_X) {
+        if (it < nix) {
             const int cy = it % CH, s = it / CH;  // consecutive lanes: consecutive rows
             stencil_window<FORCE, K, RX>(rowr + cy * S::RW + s * K, 1, a.tx_tab, acc, accu);
 #pragma unroll
@@ -127,7 +198,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
                 if (cx < CW) Fx[cy * CW + cx] = force_from<FORCE>(rowr[cy * S::RW + cx + RX], acc[k], accu[k], a.A);
             }
         } else {
-            const int jt = it - S::ITEMS_X;
+            const int jt = it - nix;
             const int cx = jt % CW, s = jt / CW;  // consecutive lanes: consecutive columns
             stencil_window<FORCE, K, RY>(colr + (s * K) * CW + cx, CW, a.ty_tab, acc, accu);
 #pragma unroll
@@ -179,11 +250,25 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  Tile t of the row-major tile order is
+// given to the workgroup that makes every XCD own one contiguous band of
+// tiles, so the +-R-row phi halos and ring cells a tile shares with its
+// neighbours are mostly in the same L2.  The map is a bijection for any count.
+constexpr int NXCD = 8;
+__device__ inline int xcd_tile(int b, int G) {
+    const int q = G / NXCD, r = G - q * NXCD;
+    const int x = b % NXCD, s = b / NXCD;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
 template <typename Real, int FORCE, int TX, int TY, int K>
 __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
     constexpr int R = Radius<Real>::value;
     __shared__ double sm[FusedShape<Real, TX, TY, K, R, R>::DOUBLES];
-    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, blockIdx.x * TX, blockIdx.y * TY, sm);
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    const int ty = t / gridDim.x, tx = t - ty * gridDim.x;
+    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, tx * TX, ty * TY, sm);
 }
 
 // Batched step: one launch advances every domain of a batch by one step.

@@ -9,6 +9,7 @@
 #include <type_traits>
 
 #include "../../include/lbm.h"
+#include "hdm_coeffs.hpp"
 #include "lbm_device.hpp"
 
 // Host state of one domain: parameters, planned constants, coefficient rows and
@@ -74,6 +75,12 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
         a.dx[j] = d->dx[j];
         a.dy[j] = d->dy[j];
     }
+    // geometric recursion along axes longer than 2R + 1 (HDM only)
+    const int R = lbm::Radius<Real>::value;
+    a.rec_x = (d->p.grad == LBM_GRAD_HDM && d->p.nx > 2 * R + 1) ? 1 : 0;
+    a.rec_y = (d->p.grad == LBM_GRAD_HDM && d->p.ny > 2 * R + 1) ? 1 : 0;
+    lbm_host::hdm_infinite(&a.rr, &a.rd1, &a.rd2, &a.rC);
+    a.rr3 = a.rr * a.rr * a.rr;
     // sign-folded tables of the blocked stencil: tab[i] = c(i - TAB_OFF)
     for (int i = 0; i < lbm::TAB; ++i) {
         const int n = i - lbm::TAB_OFF, an = n < 0 ? -n : n;

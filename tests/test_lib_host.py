@@ -66,7 +66,7 @@ def test_maxwell_rejects_supercritical():
 def test_explicit_hdm_row_matches_chasing_solve(n, prec):
     """The kernels' explicit circulant form of Eq. 20 reproduces the oracle's
     Thomas + Sherman-Morrison solve on random periodic data (to the truncation
-    tail for long lines: below 1e-16 in FP64 and 1e-7 in FP32 relative)."""
+    tail for long lines: 39 taps with FP64 populations, 28 with FP32)."""
     d = np.array(L.hdm_row(n, prec))
     rng = np.random.default_rng(n)
     u = rng.standard_normal(n)
@@ -75,7 +75,7 @@ def test_explicit_hdm_row_matches_chasing_solve(n, prec):
     got = np.zeros(n)
     for j in range(1, len(d) + 1):
         got += d[j - 1] * (u[(i + j) % n] - u[(i - j) % n])
-    tol = 3e-15 if prec == "f64" else 2e-7
+    tol = 3e-15 if prec == "f64" else 2e-11
     assert np.max(np.abs(got - ref)) < tol * np.max(np.abs(ref)), np.max(np.abs(got - ref))
 
 
