@@ -167,18 +167,18 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
     using C = Cross<double, TY>;
-    for (int i = threadIdx.x; i < TY * C::RW; i += NT) {
-        int r = i / C::RW, c = i - r * C::RW;
-        int y = min(y0 + r, a.ny - 1);
-        int xw = wrap(x0 - C::J + c, a.nx);
-        sx.row[r][c] = A.ax[(long)y * pitch + xw];
-    }
-    for (int i = threadIdx.x; i < C::CH * BX; i += NT) {
-        int r = i / BX, c = i - r * BX;
-        int yw = wrap(y0 - C::J + r, a.ny);
-        int xx = min(x0 + c, a.nx - 1);
-        sy.col[r][c] = A.ay[(long)yw * pitch + xx];
-    }
+    stage_lds<TY * C::RW, 8>(&sx.row[0][0], [&](int i) {
+        const int r = i / C::RW, c = i - r * C::RW;
+        const int y = min(y0 + r, a.ny - 1);
+        const int xw = wrap(x0 - C::J + c, a.nx);
+        return A.ax[(long)y * pitch + xw];
+    });
+    stage_lds<C::CH * BX, 8>(&sy.col[0][0], [&](int i) {
+        const int r = i / BX, c = i - r * BX;
+        const int yw = wrap(y0 - C::J + r, a.ny);
+        const int xx = min(x0 + c, a.nx - 1);
+        return A.ay[(long)yw * pitch + xx];
+    });
     __syncthreads();
     constexpr int J = C::J;
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;

@@ -147,9 +147,9 @@ struct StepArgs {
     double ty_tab[TAB];
     // Geometric form of the infinite-line row (d_j = C r^j for j >= 3), used
     // along an axis whose length exceeds 2R + 1 (there the periodic row equals
-    // it to rounding): rec_x / rec_y select it per axis.
+    // it to rounding): rec_x / rec_y select it per axis; rK = C / (1 - r).
     int rec_x, rec_y;
-    double rr, rr3, rd1, rd2, rC;
+    double rr, rr3, rr4, rd1, rd2, rK;
 };
 
 }  // namespace lbm

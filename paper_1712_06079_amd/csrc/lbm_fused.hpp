@@ -70,45 +70,50 @@ __device__ inline void stencil_window(const double* __restrict__ base, int strid
     }
 }
 
-// S outputs of Eq. 20 along one line of length > 2R + 1 in geometric form:
-// sum_j d_j (u_{i+j} - u_{i-j}) = d_1 (u_{i+1} - u_{i-1}) + d_2 (u_{i+2} - u_{i-2})
-// + C (P_i - M_i), P_i = sum_{j>=3} r^j u_{i+j}, M_i = sum_{j>=3} r^j u_{i-j},
-// evaluated by P_{i-1} = r P_i + r^3 u_{i+2} (right to left) and
-// M_{i+1} = r M_i + r^3 u_{i-2} (left to right), each started R - 2 cells
-// beyond the segment so that every output gets at least the taps j <= R.
+// S outputs of Eq. 20 along one line of length > 2R + 1 in geometric form.
+// With d_j = C r^j for j >= 3 and the first differences delta_k = u_{k+1} - u_k,
+//   sum_{j>=3} r^j (u_{i+j} - u_{i-j}) = [r^3 (u_{i+3} - u_{i-3}) + Rt_i + Lt_i] / (1 - r),
+//   Rt_i = sum_{m>=3} r^(m+1) delta_{i+m},   Lt_i = sum_{n>=4} r^n delta_{i-n},
+// so Du_i = d_1 (u_{i+1} - u_{i-1}) + d_2 (u_{i+2} - u_{i-2})
+//         + K [r^3 (u_{i+3} - u_{i-3}) + Rt_i + Lt_i],  K = C / (1 - r),
+// with Rt_{i-1} = r Rt_i + r^4 delta_{i+2} (right to left) and
+// Lt_{i+1} = r Lt_i + r^4 delta_{i-3} (left to right), each started R - 3 cells
+// beyond the segment (every output keeps at least the taps j <= R).  Working on
+// differences makes a constant line give exactly zero at every position.
 // base[k * stride] is the operand's window value at output k (k in [-R, S-1+R]).
 template <int FORCE, int S, int R>
-__device__ inline void stencil_recursive(const double* __restrict__ base, int stride, double r, double r3, double d1,
-                                         double d2, double C, double (&out)[S], double (&outu)[S]) {
-    static_assert(R >= 3, "geometric form needs R >= 3");
-    double M[S], Mu[S];
-    double m = 0.0, mu = 0.0;
+__device__ inline void stencil_recursive(const double* __restrict__ base, int stride, double r, double r3, double r4,
+                                         double d1, double d2, double K, double (&out)[S], double (&outu)[S]) {
+    static_assert(R >= 4, "geometric form needs R >= 4");
+    auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
+    auto opu = [](double v) { return v * fabs(v); };
+    double Lt[S], Ltu[S];
+    double l = 0.0, lu = 0.0;
 #pragma unroll
-    for (int i = -(R - 2); i < S - 1; ++i) {
-        const double v = base[(i - 2) * stride];
-        m = fma(r, m, r3 * (FORCE == FORCE_ZC ? v : fabs(v)));
-        if (FORCE == FORCE_HYBRID) mu = fma(r, mu, r3 * (v * fabs(v)));
+    for (int i = -(R - 3); i < S - 1; ++i) {
+        const double v2 = base[(i - 2) * stride], v3 = base[(i - 3) * stride];
+        l = fma(r, l, r4 * (op(v2) - op(v3)));
+        if (FORCE == FORCE_HYBRID) lu = fma(r, lu, r4 * (opu(v2) - opu(v3)));
         if (i + 1 >= 0) {
-            M[i + 1] = m;
-            Mu[i + 1] = mu;
+            Lt[i + 1] = l;
+            Ltu[i + 1] = lu;
         }
     }
-    double p = 0.0, pu = 0.0;
+    double q = 0.0, qu = 0.0;
 #pragma unroll
-    for (int i = S - 1 + (R - 2); i >= 1; --i) {
-        const double v = base[(i + 2) * stride];
-        p = fma(r, p, r3 * (FORCE == FORCE_ZC ? v : fabs(v)));
-        if (FORCE == FORCE_HYBRID) pu = fma(r, pu, r3 * (v * fabs(v)));
+    for (int i = S - 1 + (R - 3); i >= 1; --i) {
+        const double v3 = base[(i + 3) * stride], v2 = base[(i + 2) * stride];
+        q = fma(r, q, r4 * (op(v3) - op(v2)));
+        if (FORCE == FORCE_HYBRID) qu = fma(r, qu, r4 * (opu(v3) - opu(v2)));
         const int o = i - 1;
         if (o < S) {
             const double a1 = base[(o + 1) * stride], b1 = base[(o - 1) * stride];
             const double a2 = base[(o + 2) * stride], b2 = base[(o - 2) * stride];
-            if (FORCE == FORCE_ZC)
-                out[o] = d1 * (a1 - b1) + d2 * (a2 - b2) + C * (p - M[o]);
-            else
-                out[o] = d1 * (fabs(a1) - fabs(b1)) + d2 * (fabs(a2) - fabs(b2)) + C * (p - M[o]);
+            const double a3 = base[(o + 3) * stride], b3 = base[(o - 3) * stride];
+            out[o] = d1 * (op(a1) - op(b1)) + d2 * (op(a2) - op(b2)) + K * (r3 * (op(a3) - op(b3)) + q + Lt[o]);
             if (FORCE == FORCE_HYBRID)
-                outu[o] = d1 * (a1 * fabs(a1) - b1 * fabs(b1)) + d2 * (a2 * fabs(a2) - b2 * fabs(b2)) + C * (pu - Mu[o]);
+                outu[o] = d1 * (opu(a1) - opu(b1)) + d2 * (opu(a2) - opu(b2)) +
+                          K * (r3 * (opu(a3) - opu(b3)) + qu + Ltu[o]);
         }
     }
 }
@@ -150,16 +155,16 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     }
 
     // Phase 1: phi cross.
-    for (int i = tid; i < CH * S::RW; i += NT) {
+    stage_lds<CH * S::RW, 8>(rowr, [&](int i) {
         const int r = i / S::RW, c = i - r * S::RW;
         const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
-        rowr[i] = a.phi_in[(long)yw * pitch + xw];
-    }
-    for (int i = tid; i < S::VH * CW; i += NT) {
+        return a.phi_in[(long)yw * pitch + xw];
+    });
+    stage_lds<S::VH * CW, 8>(colr, [&](int i) {
         const int r = i / CW, c = i - r * CW;
         const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
-        colr[i] = a.phi_in[(long)yw * pitch + xw];
-    }
+        return a.phi_in[(long)yw * pitch + xw];
+    });
     __syncthreads();
 
     // Phase 2: gradients and force.  Axes longer than 2R + 1 use the geometric
@@ -171,8 +176,8 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
         if (it < nix && a.rec_x) {
             const int cy = it % CH, s = it / CH;
             double out[S::SX], outu[S::SX];
-            stencil_recursive<FORCE, S::SX, RX>(rowr + cy * S::RW + RX + s * S::SX, 1, a.rr, a.rr3, a.rd1, a.rd2, a.rC,
-                                                out, outu);
+            stencil_recursive<FORCE, S::SX, RX>(rowr + cy * S::RW + RX + s * S::SX, 1, a.rr, a.rr3, a.rr4, a.rd1, a.rd2,
+                                                a.rK, out, outu);
 #pragma unroll
             for (int k = 0; k < S::SX; ++k) {
                 const int cx = s * S::SX + k;
@@ -183,7 +188,8 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
         if (it >= nix && a.rec_y) {
             const int cx = it - nix;
             double out[CH], outu[CH];
-            stencil_recursive<FORCE, CH, RY>(colr + RY * CW + cx, CW, a.rr, a.rr3, a.rd1, a.rd2, a.rC, out, outu);
+            stencil_recursive<FORCE, CH, RY>(colr + RY * CW + cx, CW, a.rr, a.rr3, a.rr4, a.rd1, a.rd2, a.rK,
+                                             out, outu);
 #pragma unroll
             for (int k = 0; k < CH; ++k) Fy[k * CW + cx] = force_from<FORCE>(colr[(k + RY) * CW + cx], out[k], outu[k], a.A);
             continue;

@@ -79,8 +79,11 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     const int R = lbm::Radius<Real>::value;
     a.rec_x = (d->p.grad == LBM_GRAD_HDM && d->p.nx > 2 * R + 1) ? 1 : 0;
     a.rec_y = (d->p.grad == LBM_GRAD_HDM && d->p.ny > 2 * R + 1) ? 1 : 0;
-    lbm_host::hdm_infinite(&a.rr, &a.rd1, &a.rd2, &a.rC);
+    double C = 0.0;
+    lbm_host::hdm_infinite(&a.rr, &a.rd1, &a.rd2, &C);
     a.rr3 = a.rr * a.rr * a.rr;
+    a.rr4 = a.rr3 * a.rr;
+    a.rK = C / (1.0 - a.rr);
     // sign-folded tables of the blocked stencil: tab[i] = c(i - TAB_OFF)
     for (int i = 0; i < lbm::TAB; ++i) {
         const int n = i - lbm::TAB_OFF, an = n < 0 ? -n : n;

@@ -78,22 +78,46 @@ struct Cross {
     double col[CH][BX];
 };
 
+// Workgroup copy dst[i] = src(i), i in [0, N), where src(i) reads global
+// memory.  Each thread takes the elements i = tid + j NT and issues the loads of
+// B of them before the first LDS store, so the loads are in flight together
+// instead of one global-memory latency per element.
+template <int N, int B, typename Src>
+__device__ inline void stage_lds(double* __restrict__ dst, Src src) {
+    constexpr int PER = (N + NT - 1) / NT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j0 = 0; j0 < PER; j0 += B) {
+        double v[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int i = tid + (j0 + j) * NT;
+            if (j0 + j < PER && i < N) v[j] = src(i);
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int i = tid + (j0 + j) * NT;
+            if (j0 + j < PER && i < N) dst[i] = v[j];
+        }
+    }
+}
+
 template <typename Real, int TY>
 __device__ inline void stage_cross(Cross<Real, TY>& s, const double* __restrict__ phi, int x0, int y0, int nx,
                                    int ny, int pitch) {
     using C = Cross<Real, TY>;
-    for (int i = threadIdx.x; i < TY * C::RW; i += NT) {
-        int r = i / C::RW, c = i - r * C::RW;
-        int y = min(y0 + r, ny - 1);
-        int x = wrap(x0 - C::J + c, nx);
-        s.row[r][c] = phi[(long)y * pitch + x];
-    }
-    for (int i = threadIdx.x; i < C::CH * BX; i += NT) {
-        int r = i / BX, c = i - r * BX;
-        int y = wrap(y0 - C::J + r, ny);
-        int x = min(x0 + c, nx - 1);
-        s.col[r][c] = phi[(long)y * pitch + x];
-    }
+    stage_lds<TY * C::RW, 8>(&s.row[0][0], [&](int i) {
+        const int r = i / C::RW, c = i - r * C::RW;
+        const int y = min(y0 + r, ny - 1);
+        const int x = wrap(x0 - C::J + c, nx);
+        return phi[(long)y * pitch + x];
+    });
+    stage_lds<C::CH * BX, 8>(&s.col[0][0], [&](int i) {
+        const int r = i / BX, c = i - r * BX;
+        const int y = wrap(y0 - C::J + r, ny);
+        const int x = min(x0 + c, nx - 1);
+        return phi[(long)y * pitch + x];
+    });
 }
 
 // Interaction force at tile cell (r, lx) from the staged cross (double arithmetic):
