@@ -30,7 +30,8 @@ import lbm_inputs as I  # noqa: E402
 METRIC = "MLUPS & %HBM roofline (FP64/FP32); batched domains/s; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
 Q = 9
-KERNEL_SOURCES = ["lbm_fused.hpp", "lbm_kernels.hpp", "lbm_device.hpp"]
+KERNEL_SOURCES = ["lbm_march.hpp", "lbm_fused.hpp", "lbm_kernels.hpp", "lbm_device.hpp"]
+KERNEL_NAMES = {0: "k_march", 1: "k_collide", 2: "k_fused", 3: "k_march"}
 
 
 def kernel_hash() -> str:
@@ -68,7 +69,7 @@ def workload(name: str, seed: int = 2024):
     raise ValueError(name)
 
 
-def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0):
+def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0, chunks: int = 0):
     import torch
 
     import paper_1712_06079_amd as L
@@ -78,6 +79,7 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     t = lambda a: None if a is None else torch.from_numpy(a).to(dev)  # noqa: E731
     d = L.Domain(p, t(rho0), t(ux0), t(uy0))
     d.set_kernel(variant, tile)
+    d.set_chunks(chunks)
     stream = torch.cuda.current_stream()
     d.step(warmup)
     torch.cuda.synchronize()
@@ -111,10 +113,10 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     }
 
 
-def traffic_from_profile(name: str, prec: str):
+def traffic_from_profile(kernel: str, name: str, prec: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_fused_{name}_{prec}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{prec}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -301,8 +303,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c5", choices=["c5", "c2"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--variant", type=int, default=0, help="0 fused kernel, 1 two-pass reference pair")
-    ap.add_argument("--tile", type=int, default=0, help="rows per fused tile (0 = default)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="0 automatic (strip march here), 1 two-pass reference, 2 fused tiles, 3 fused strip march")
+    ap.add_argument("--tile", type=int, default=0, help="rows per tile or marching block (0 = default)")
+    ap.add_argument("--chunks", type=int, default=0, help="y chunks per strip of the marching kernel (0 = automatic)")
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle sample steps (0 = skip)")
     ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-probe", action="store_true", help="only run the streaming-copy calibration kernel")
@@ -319,14 +323,14 @@ def main():
         print("bench.py: launched with WORLD_SIZE > 1; this build runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
-    r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile)
+    r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile, args.chunks)
     print(f"[bench] {args.workload} {args.prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
           f"kernel {r['launch_ms_mean']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
     p = r["params"]
     other = None
     if not args.no_other_prec:
         op = "f32" if args.prec == "f64" else "f64"
-        o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile)
+        o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile, args.chunks)
         print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, kernel {o['launch_ms_mean']:.4f} ms, "
               f"{o['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
         other = {"storage": op, "dtype": "f64", "value": round(o["mlups"], 1), "ms_per_step": round(o["ms_per_step"], 5),
@@ -342,17 +346,18 @@ def main():
         print(f"[bench] adjoint/forward step {adjoint['adjoint_over_forward']}, gradient/forward "
               f"{adjoint['gradient_over_forward']}", file=sys.stderr, flush=True)
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
-    traffic = traffic_from_profile(args.workload, args.prec)
+    kname = KERNEL_NAMES.get(args.variant, "k_march")
+    traffic = traffic_from_profile(kname, args.workload, args.prec)
     line = {
         "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": r["desc"], "storage": args.prec, "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
-                   "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": "fused" if args.variant == 0 else "two-pass",
+                   "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": kname,
                    "finite": r["finite"]},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_fused", "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+                     "kernel": kname, "alg_bytes_per_launch": r["alg_bytes_per_launch"],
                      "launch_ms": round(r["launch_ms_mean"], 5)},
         "cpu_baseline": cpu,
     }

@@ -138,10 +138,25 @@ lbm_status lbm_set_populations(lbm_domain* d, const double* f, hipStream_t strea
 /* Number of steps taken since lbm_init (host). */
 int64_t lbm_step_count(const lbm_domain* d);
 
-/* Select the step kernel (host; for tuning and tests): variant 0 = fused
- * single-pass kernel, 1 = two-pass reference kernel pair; tile_y = rows per
- * workgroup tile (0 = default).  LBM_EINVAL for unknown values. */
+/* Select the step kernel (host; for tuning and tests).  All variants compute
+ * the same step (Sec. 2-3); they differ in how the lattice is decomposed:
+ *   0  fused single pass, chosen automatically (the default): the strip-
+ *      marching kernel when the HDM gradient takes its geometric form along y
+ *      (grad = HDM and ny > 2R + 1, R = 39 for FP64 and 28 for FP32
+ *      populations), otherwise independent tiles;
+ *   1  two-pass reference pair (force + collision + push streaming, then the
+ *      potential field), tile_y <= 8 or 16 rows;
+ *   2  fused single pass over independent 64 x tile_y tiles, tile_y in
+ *      {0 (default), 4, 8, 16};
+ *   3  fused strip-marching kernel, tile_y = rows per block in {0 (4), 4, 8};
+ *      LBM_EUNSUPPORTED from lbm_step when the domain is not eligible.
+ * LBM_EINVAL for unknown values. */
 lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
+
+/* Number of y chunks each 64-column strip is split into by the marching
+ * kernel (host; for tuning and tests): 0 = automatic (one full set of resident
+ * workgroups), otherwise min(nchunk, ny).  LBM_EINVAL for nchunk < 0. */
+lbm_status lbm_set_chunks(lbm_domain* d, int32_t nchunk);
 
 /* Check the current density for non-finite values (synchronises `stream`):
  * *ok = 1 if every rho is finite, else 0 (and the call returns LBM_ENONFINITE). */

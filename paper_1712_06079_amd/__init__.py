@@ -83,6 +83,7 @@ def library():
         L.lbm_step_count.argtypes = [_VP]
         L.lbm_step_count.restype = C.c_int64
         L.lbm_set_kernel.argtypes = [_VP, C.c_int32, C.c_int32]
+        L.lbm_set_chunks.argtypes = [_VP, C.c_int32]
         L.lbm_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
         L.lbm_state_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
         L.lbm_save_state.argtypes = [_VP, _VP, _VP]
@@ -94,7 +95,7 @@ def library():
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
-                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_check_finite",
+                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
                    "lbm_adjoint_step", "lbm_adjoint_rho0"):
             getattr(L, fn).restype = C.c_int
@@ -181,7 +182,12 @@ class Domain:
         return self._h
 
     def set_kernel(self, variant: int = 0, tile_y: int = 0):
+        """0 automatic, 1 two-pass reference, 2 fused tiles, 3 fused strip march."""
         check(library().lbm_set_kernel(self._h, variant, tile_y))
+
+    def set_chunks(self, nchunk: int = 0):
+        """y chunks per strip of the marching kernel (0 = automatic)."""
+        check(library().lbm_set_chunks(self._h, nchunk))
 
     def step(self, n: int = 1, stream=None):
         check(library().lbm_step(self._h, int(n), _stream(stream)))

@@ -15,6 +15,7 @@
 #include "hdm_coeffs.hpp"
 #include "lbm_adjoint.hpp"
 #include "lbm_fused.hpp"
+#include "lbm_march.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 
@@ -108,6 +109,40 @@ void launch_ref(lbm_domain* d, const lbm::StepArgs<Real>& a, hipStream_t s) {
     hipLaunchKernelGGL((lbm::k_collide<Real, FORCE, TY>), grid, dim3(lbm::NT), 0, s, a);
 }
 
+// The marching kernel needs the geometric form along y (HDM, ny > 2R + 1).
+bool march_eligible(const lbm_domain* d) {
+    const int R = d->p.prec == LBM_F32 ? lbm::Radius<float>::value : lbm::Radius<double>::value;
+    return d->p.grad == LBM_GRAD_HDM && d->p.ny > 2 * R + 1;
+}
+
+// Rows per marching block: 4 by default (two FP64 or three FP32-storage
+// workgroups per CU fit in LDS).
+int march_rows(const lbm_domain* d) { return d->tile_y ? d->tile_y : 4; }
+
+// y chunks per strip: by default as many as make the grid one full set of
+// resident workgroups (strips x chunks ~ CUs x workgroups per CU).
+template <typename Real, int FORCE>
+lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
+    if (d->chunks > 0) {
+        *nchunk = d->chunks < d->p.ny ? d->chunks : d->p.ny;
+        return LBM_OK;
+    }
+    int& per_cu = ty == 4 ? d->march_occ[0] : d->march_occ[1];  // cached occupancy query
+    if (per_cu == 0) {
+        if (ty == 4)
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 4>, lbm::NT, 0));
+        else
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 8>, lbm::NT, 0));
+        if (per_cu < 1) per_cu = 1;
+    }
+    const long target = (long)d->ncu * per_cu;
+    long n = (target + d->nxb - 1) / d->nxb;
+    if (n > d->p.ny) n = d->p.ny;
+    if (n < 1) n = 1;
+    *nchunk = (int)n;
+    return LBM_OK;
+}
+
 lbm_status step_once(lbm_domain* d, hipStream_t s) {
     const int in = d->cur, out = 1 - d->cur;
     if (d->variant == 1) {
@@ -122,14 +157,25 @@ lbm_status step_once(lbm_domain* d, hipStream_t s) {
         d->cur = out;
         return launch_phi(d, out, s);
     }
+    const bool march = d->variant == 3 || (d->variant == 0 && march_eligible(d));
+    if (march && !march_eligible(d))
+        return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and ny > 2R + 1");
     lbm_status st = LBM_OK;
     dispatch(d, [&](auto real, auto force) {
         using Real = decltype(real);
         constexpr int F = decltype(force)::value;
         auto a = make_args<Real>(d, in, out);
-        if (!lbm::launch_fused<Real, F>(a, d->tile_y, s)) st = LBM_EUNSUPPORTED;
+        if (march) {
+            const int ty = march_rows(d);
+            int nchunk = 1;
+            st = march_chunks<Real, F>(d, ty, &nchunk);
+            if (st == LBM_OK && !lbm::launch_march<Real, F>(a, ty, nchunk, s))
+                st = fail(LBM_EUNSUPPORTED, "marching kernel: unsupported block height %d", ty);
+        } else if (!lbm::launch_fused<Real, F>(a, d->variant == 0 ? 0 : d->tile_y, s)) {
+            st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", d->tile_y);
+        }
     });
-    if (st != LBM_OK) return fail(st, "fused kernel: unsupported tile height %d", d->tile_y);
+    if (st != LBM_OK) return st;
     HIP_TRY(hipGetLastError());
     d->cur = out;
     return LBM_OK;
@@ -191,6 +237,11 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
     if ((p->eos == LBM_EOS_PR || p->eos == LBM_EOS_RKS) && !(p->T < 4.0 * Tc))
         return fail(LBM_EINVAL, "T = %g is outside the alpha(T_r) range", p->T);
 
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (ncu < 1) ncu = 1;
+
     lbm_domain* d = new (std::nothrow) lbm_domain;
     if (!d) return fail(LBM_EINVAL, "out of host memory");
     std::memset(d, 0, sizeof(*d));
@@ -204,6 +255,8 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
     d->steps = 0;
     d->variant = 0;
     d->tile_y = 0;
+    d->chunks = 0;
+    d->ncu = ncu;
     d->ws = static_cast<char*>(workspace);
     d->ws_bytes = workspace_bytes;
     d->off_f[0] = 0;
@@ -315,10 +368,21 @@ int64_t lbm_step_count(const lbm_domain* d) { return d ? d->steps : -1; }
 
 lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y) {
     if (!d) return fail(LBM_EINVAL, "NULL domain");
-    if (variant < 0 || variant > 1) return fail(LBM_EINVAL, "unknown kernel variant %d", variant);
+    if (variant < 0 || variant > 3) return fail(LBM_EINVAL, "unknown kernel variant %d", variant);
     if (tile_y < 0 || tile_y > 64) return fail(LBM_EINVAL, "tile_y %d out of range", tile_y);
+    if (variant == 2 && !(tile_y == 0 || tile_y == 4 || tile_y == 8 || tile_y == 16))
+        return fail(LBM_EINVAL, "tile kernel: tile_y must be 0, 4, 8 or 16 (got %d)", tile_y);
+    if (variant == 3 && !(tile_y == 0 || tile_y == 4 || tile_y == 8))
+        return fail(LBM_EINVAL, "marching kernel: block rows must be 0, 4 or 8 (got %d)", tile_y);
     d->variant = variant;
     d->tile_y = tile_y;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_chunks(lbm_domain* d, int32_t nchunk) {
+    if (!d) return fail(LBM_EINVAL, "NULL domain");
+    if (nchunk < 0) return fail(LBM_EINVAL, "chunk count %d < 0", nchunk);
+    d->chunks = nchunk;
     return LBM_OK;
 }
 

@@ -141,30 +141,42 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
 
-    // Phase 0: loads of f_t for this thread's collision cells.
-    Real f[S::NC][Q];
-#pragma unroll
-    for (int i = 0; i < S::NC; ++i) {
-        const int c = tid + i * NT;
-        if (c < S::NCELL) {
-            const int cy = c / CW, cx = c - cy * CW;
-            const int xw = wrap(x0 - 1 + cx, nx), yw = wrap(y0 - 1 + cy, ny);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) f[i][q] = a.f_in[fidx(xw, yw, q, nxb)];
-        }
-    }
-
-    // Phase 1: phi cross.
-    stage_lds<CH * S::RW, 8>(rowr, [&](int i) {
+    // Phase 1 loads: the potential cross, issued first because it is needed
+    // first (vector loads retire in order, so a wait for the cross must not
+    // also wait for the populations).
+    StageRegs<CH * S::RW> srow;
+    StageRegs<S::VH * CW> scol;
+    stage_issue(srow, [&](int i) {
         const int r = i / S::RW, c = i - r * S::RW;
         const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
         return a.phi_in[(long)yw * pitch + xw];
     });
-    stage_lds<S::VH * CW, 8>(colr, [&](int i) {
+    stage_issue(scol, [&](int i) {
         const int r = i / CW, c = i - r * CW;
         const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
         return a.phi_in[(long)yw * pitch + xw];
     });
+
+    // Keep the compiler from moving cross loads behind population loads.
+    __builtin_amdgcn_sched_barrier(0);
+
+    // Phase 0: loads of f_t for this thread's collision cells (consumed in
+    // phase 3, in flight during phases 1-2).
+    Real f[S::NC][Q];
+#pragma unroll
+    for (int i = 0; i < S::NC; ++i) {
+        const int c = min(tid + i * NT, S::NCELL - 1);  // past the end: a duplicate, never used
+        const int cy = c / CW, cx = c - cy * CW;
+        const int xw = wrap(x0 - 1 + cx, nx), yw = wrap(y0 - 1 + cy, ny);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[i][q] = a.f_in[fidx(xw, yw, q, nxb)];
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+
+    // Phase 1: the cross into LDS.
+    stage_commit(rowr, srow);
+    stage_commit(colr, scol);
     __syncthreads();
 
     // Phase 2: gradients and force.  Axes longer than 2R + 1 use the geometric
@@ -172,7 +184,13 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     // column per y item); shorter axes the explicit K-blocked window.
     const int nix = a.rec_x ? S::RITEMS_X : S::ITEMS_X;
     const int niy = a.rec_y ? S::RITEMS_Y : S::ITEMS_Y;
-    for (int it = tid; it < nix + niy; it += NT) {
+    // y items start at a wavefront boundary so that no wavefront runs both
+    // the x and the y branch (they would execute one after the other).
+    const int ybase = (nix + BX - 1) & ~(BX - 1);
+    const int nit = ybase + niy;
+    for (int jt = tid; jt < nit; jt += NT) {
+        if (jt >= nix && jt < ybase) continue;
+        const int it = jt < nix ? jt : jt - ybase + nix;
         if (it < nix && a.rec_x) {
             const int cy = it % CH, s = it / CH;
             double out[S::SX], outu[S::SX];
@@ -204,8 +222,8 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
                 if (cx < CW) Fx[cy * CW + cx] = force_from<FORCE>(rowr[cy * S::RW + cx + RX], acc[k], accu[k], a.A);
             }
         } else {
-            const int jt = it - nix;
-            const int cx = jt % CW, s = jt / CW;  // consecutive lanes: consecutive columns
+            const int yt = it - nix;
+            const int cx = yt % CW, s = yt / CW;  // consecutive lanes: consecutive columns
             stencil_window<FORCE, K, RY>(colr + (s * K) * CW + cx, CW, a.ty_tab, acc, accu);
 #pragma unroll
             for (int k = 0; k < K; ++k) {

@@ -20,8 +20,11 @@ struct lbm_domain {
     int nxb, pitch;
     int cur;           // index of the buffer pair holding the current state
     int64_t steps;
-    int variant;       // 0 fused, 1 two-pass reference
-    int tile_y;        // rows per tile (0 = default)
+    int variant;       // 0 fused (automatic), 1 two-pass reference, 2 fused tiles, 3 fused march
+    int tile_y;        // rows per tile or marching block (0 = default)
+    int chunks;        // y chunks per strip of the marching kernel (0 = automatic)
+    int ncu;           // compute units of the device
+    int march_occ[2];  // resident marching workgroups per CU (block rows 4, 8; 0 = not queried)
     char* ws;
     size_t ws_bytes;
     size_t off_f[2], off_phi[2], off_part, off_scr;

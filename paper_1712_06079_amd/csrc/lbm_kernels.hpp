@@ -82,6 +82,35 @@ struct Cross {
 // memory.  Each thread takes the elements i = tid + j NT and issues the loads of
 // B of them before the first LDS store, so the loads are in flight together
 // instead of one global-memory latency per element.
+template <int N>
+struct StageRegs {
+    static constexpr int PER = (N + NT - 1) / NT;
+    double v[PER];
+};
+
+// Split form of the copy: stage_issue loads every element of this thread
+// into registers, stage_commit stores them, so other loads (issued after
+// stage_issue) do not delay the wait before the LDS stores.
+template <int N, typename Src>
+__device__ inline void stage_issue(StageRegs<N>& s, Src src) {
+#pragma unroll
+    for (int j = 0; j < StageRegs<N>::PER; ++j) {
+        // past the end: reload the last element (kept unconditional so the
+        // loads form one straight-line batch; the duplicate is not stored)
+        const int i = min((int)threadIdx.x + j * NT, N - 1);
+        s.v[j] = src(i);
+    }
+}
+
+template <int N>
+__device__ inline void stage_commit(double* __restrict__ dst, const StageRegs<N>& s) {
+#pragma unroll
+    for (int j = 0; j < StageRegs<N>::PER; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (i < N) dst[i] = s.v[j];
+    }
+}
+
 template <int N, int B, typename Src>
 __device__ inline void stage_lds(double* __restrict__ dst, Src src) {
     constexpr int PER = (N + NT - 1) / NT;

@@ -32,9 +32,10 @@ def dev(a):
     return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def gpu_run(po, rho0, steps, prec="f64", ux0=None, uy0=None, variant=0, tile=0):
+def gpu_run(po, rho0, steps, prec="f64", ux0=None, uy0=None, variant=0, tile=0, chunks=0):
     d = L.Domain(lib_params(po, prec), dev(rho0), dev(ux0), dev(uy0))
     d.set_kernel(variant, tile)
+    d.set_chunks(chunks)
     d.step(steps)
     m = d.moments()
     f = d.populations()
@@ -68,7 +69,7 @@ def c1_oracle():
     return po, rho0, oracle_run(po, rho0, 2000)
 
 
-@pytest.mark.parametrize("variant,tile", [(0, 0), (0, 4), (0, 16), (1, 8), (1, 16)])
+@pytest.mark.parametrize("variant,tile", [(0, 0), (2, 4), (2, 16), (1, 8), (1, 16)])
 def test_c1_fp64(c1_oracle, variant, tile):
     """64x64 VDW T_r = 0.9 slab, SC + HDM, 2000 steps: densities and mass within 1e-12."""
     po, rho0, ref = c1_oracle
@@ -123,12 +124,63 @@ def test_shapes(nx, ny, prec):
     assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
 
 
-@pytest.mark.parametrize("variant,tile", [(0, 4), (0, 8), (0, 16), (1, 8), (1, 16)])
+@pytest.mark.parametrize("variant,tile", [(2, 4), (2, 8), (2, 16), (1, 8), (1, 16)])
 def test_kernel_variants_agree(variant, tile):
     po, rho0, ux0, uy0 = variant_case("pr", "zc", 150, 70, seed=3)
     ref = oracle_run(po, rho0, 30, ux0, uy0)
     got = gpu_run(po, rho0, 30, "f64", ux0, uy0, variant=variant, tile=tile)
     assert rel_err(got["rho"], ref["rho"]) < 1e-12
+
+
+# The strip-marching kernel: y longer than 2R + 1 (R = 39 FP64, 28 FP32), ragged
+# strips in x, chunk counts from one per strip to one row per chunk.
+MARCH_CASES = [
+    (96, 150, 4, 0), (96, 150, 8, 0), (150, 90, 4, 1), (150, 90, 8, 3), (70, 97, 4, 7),
+    (200, 83, 4, 83), (33, 130, 8, 5), (64, 256, 4, 2), (130, 100, 8, 100),
+]
+
+
+@pytest.mark.parametrize("nx,ny,ty,chunks", MARCH_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_march_matches_oracle(nx, ny, ty, chunks, prec):
+    po, rho0, ux0, uy0 = variant_case("cs", "sc", nx, ny, seed=nx + 3 * ny + ty)
+    ref = oracle_run(po, rho0, 40, ux0, uy0)
+    got = gpu_run(po, rho0, 40, prec, ux0, uy0, variant=3, tile=ty, chunks=chunks)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+    assert np.max(np.abs(got["f"] - ref["f"])) < TOL[prec] * np.max(np.abs(ref["f"]))
+
+
+@pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
+@pytest.mark.parametrize("eos", ["vdw", "pr", "rk"])
+def test_march_forces(eos, force):
+    """Every force on the marching kernel, short x axis (explicit x window) and
+    long x axis (recursive), FP64."""
+    for nx, ny in ((40, 100), (140, 88)):
+        po, rho0, ux0, uy0 = variant_case(eos, force, nx, ny, seed=nx + ny)
+        ref = oracle_run(po, rho0, 30, ux0, uy0)
+        got = gpu_run(po, rho0, 30, "f64", ux0, uy0, variant=3, tile=4, chunks=3)
+        assert rel_err(got["rho"], ref["rho"]) < 1e-12
+
+
+def test_march_rejects_short_y():
+    po, rho0, _, _ = variant_case("vdw", "sc", 96, 64, seed=1)
+    d = L.Domain(lib_params(po), dev(rho0))
+    d.set_kernel(3, 4)
+    with pytest.raises(L.LBMError) as e:
+        d.step(1)
+    assert e.value.status == 5
+
+
+def test_march_invariance_bitwise():
+    """Noise-free slabs on the marching kernel: a y-slab stays bitwise
+    x-invariant, an x-slab bitwise y-invariant."""
+    po = PINS.c1_params(nx=128, ny=96)
+    rv, rl, _ = O.maxwell(po, po.T)
+    f = gpu_run(po, I.slab(128, 96, rv, rl, 5.0, axis="y"), 200, variant=3, chunks=5)["f"]
+    assert np.all(f == f[:, :, :1])
+    po = PINS.c1_params(nx=96, ny=128)
+    f = gpu_run(po, I.slab(96, 128, rv, rl, 5.0, axis="x"), 200, variant=3, chunks=5)["f"]
+    assert np.all(f == f[:, :1, :])
 
 
 def test_cdm_gradient():
