@@ -148,7 +148,7 @@ int64_t lbm_step_count(const lbm_domain* d);
  *      potential field), tile_y <= 8 or 16 rows;
  *   2  fused single pass over independent 64 x tile_y tiles, tile_y in
  *      {0 (default), 4, 8, 16};
- *   3  fused strip-marching kernel, tile_y = rows per block in {0 (4), 4, 8};
+ *   3  fused strip-marching kernel, tile_y = rows per block in {0 (8), 4, 8};
  *      LBM_EUNSUPPORTED from lbm_step when the domain is not eligible.
  * LBM_EINVAL for unknown values. */
 lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);

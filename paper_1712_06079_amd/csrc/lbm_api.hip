@@ -109,15 +109,17 @@ void launch_ref(lbm_domain* d, const lbm::StepArgs<Real>& a, hipStream_t s) {
     hipLaunchKernelGGL((lbm::k_collide<Real, FORCE, TY>), grid, dim3(lbm::NT), 0, s, a);
 }
 
-// The marching kernel needs the geometric form along y (HDM, ny > 2R + 1).
-bool march_eligible(const lbm_domain* d) {
-    const int R = d->p.prec == LBM_F32 ? lbm::Radius<float>::value : lbm::Radius<double>::value;
-    return d->p.grad == LBM_GRAD_HDM && d->p.ny > 2 * R + 1;
-}
+// Rows per marching block (default 8: the longest block that keeps two
+// workgroups per CU in LDS and registers, for both population precisions).
+int march_rows(const lbm_domain* d) { return d->tile_y ? d->tile_y : 8; }
 
-// Rows per marching block: 4 by default (two FP64 or three FP32-storage
-// workgroups per CU fit in LDS).
-int march_rows(const lbm_domain* d) { return d->tile_y ? d->tile_y : 4; }
+// The marching kernel needs the geometric form along y (HDM, ny > 2R + 1) and
+// a y period longer than its look-ahead.
+bool march_eligible(const lbm_domain* d) {
+    if (d->p.grad != LBM_GRAD_HDM) return false;
+    return d->p.prec == LBM_F32 ? lbm::march_fits<float>(d->p.ny, march_rows(d))
+                                : lbm::march_fits<double>(d->p.ny, march_rows(d));
+}
 
 // y chunks per strip: by default as many as make the grid one full set of
 // resident workgroups (strips x chunks ~ CUs x workgroups per CU).
@@ -159,7 +161,7 @@ lbm_status step_once(lbm_domain* d, hipStream_t s) {
     }
     const bool march = d->variant == 3 || (d->variant == 0 && march_eligible(d));
     if (march && !march_eligible(d))
-        return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and ny > 2R + 1");
+        return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and a longer y axis (ny = %d)", d->p.ny);
     lbm_status st = LBM_OK;
     dispatch(d, [&](auto real, auto force) {
         using Real = decltype(real);

@@ -3,71 +3,93 @@
 //
 // A workgroup owns one 64-column strip of the lattice over the rows [ys, ye) of
 // one y chunk and walks down it in blocks of TY rows.  Compared with
-// independent tiles (lbm_fused.hpp) this
-//  - collides every row once (a tile also collides the ring rows above and
-//    below it, which its neighbours collide again),
-//  - keeps the potential rows the y stencil needs in an LDS ring, so a row is
-//    read once per strip instead of once per tile and halo,
-//  - carries the left-to-right half of the y recursion from block to block,
-//  - and overlaps the loads of block k+1 with the arithmetic of block k.
+// independent tiles (lbm_fused.hpp) this collides every row once, reads the
+// potential rows of the y stencil once per strip, and overlaps the loads of
+// block k+1 with the arithmetic of block k.
 //
-// Block k covers the collision rows yb .. yb+TY-1 (yb = ys - 1 + k TY) and the
-// 66 collision columns x0-1 .. x0+64:
-//  1  issue the loads of block k+1: its populations, the potential rows that
-//     enter the ring, its x bar (rows widened by +-R in x);
-//  2  forces: d/dx from the bar (geometric recursion or the explicit window),
-//     d/dy from the ring (forward state carried over, backward sum restarted
-//     R - 3 rows below the block), then Eq. 22 / Eq. 7 / Eq. 9;
-//  3  EDM-BGK collision of the TY x 66 cells into the post-collision ring,
-//     which holds rows yb-2 .. yb+TY-1;
+// The y derivative.  In the difference form of the geometric recursion (see
+// stencil_recursive) the output at row o needs the forward sum Lt_o, carried
+// from block to block, and the backward sum q(o+1), with
+//   q(i) = sum_{n>=0} r^n t_{i+n},   t_i = r^4 (u_{i+3} - u_{i+2}).
+// Grouping the t of the TY-row blocks ahead of the current block,
+//   W_j = sum_{n<TY} r^n t_{yb+1+jTY+n}   (j = 1 .. NB),
+//   q(yb+1+TY) = sum_j r^{(j-1)TY} W_j,
+// so a column keeps a window of NB block sums (one new W per block, from the
+// TY rows that arrive NB blocks ahead) and a window of the TY+8 potential rows
+// around the block, all in registers; q inside the block is the recursion
+// over its own TY rows.  NB TY + 3 >= R keeps at least R taps for every output.
+//
+// Lanes (256 threads, four wavefronts):
+//  wave 0   one interior column each (x0 .. x0+63): d/dy -> Fy in LDS;
+//  wave 1   lanes 0 .. 2TY-1 own the ring cells (columns x0-1 and x0+64, TY
+//           rows): their d/dy, an explicit d/dx over the x bar, and their
+//           collision, all during the force phase;
+//  waves 2-3  d/dx of the interior: per row and 8-column segment one lane runs
+//           the forward and its neighbour the backward recursion in lockstep
+//           (or the explicit window on a short x axis);
+//  all      one interior cell each for collision (forces combined from the
+//           partial sums) and streaming.
+// Per block (collision rows yb .. yb+TY-1, yb = ys - 1 + k TY):
+//  1  issue the loads of block k+1 (ring-cell populations, x bar, the new
+//     potential rows of each column; its interior populations follow in 4);
+//  2  forces (and the ring cells' collision);
+//  3  collision of the interior cells into the post-collision ring (rows
+//     yb-2 .. yb+TY-1);
 //  4  pull streaming of rows yb-1 .. yb+TY-2 (stored when inside [ys, ye)),
 //     then rho -> U -> phi_{t+1} of those cells;
-//  5  commit the potential loads of step 1 into LDS.
-// Rows above ys and below ye are read with periodic wrap; a chunk starts one
-// block early (rows ys-1 ..) and its first rows feed only cells it does not
-// store.
+//  5  commit the loads of step 1 (LDS, register windows).
 #pragma once
 
 #include "lbm_fused.hpp"
 
 namespace lbm {
 
-template <typename Real, int TY, int R>
+template <typename Real, int FORCE, int TY, int R>
 struct MarchShape {
     static constexpr int CW = BX + 2;                       // collision columns x0-1 .. x0+64
-    static constexpr int NCELL = TY * CW;                   // collision cells per block
-    static constexpr int NC = (NCELL + NT - 1) / NT;        // per thread
-    static constexpr int NI = (TY * BX + NT - 1) / NT;      // streamed cells per thread
-    static constexpr int RING = TY + R + 4;                 // phi rows yb-4 .. yb+TY+R-1
+    static constexpr int NI = TY * BX / NT;                 // interior cells per thread
     static constexpr int PR = TY + 2;                       // post-collision rows yb-2 .. yb+TY-1
+    static constexpr int NB = (R - 3 + TY - 1) / TY;        // block sums ahead (NB TY + 3 >= R)
+    static constexpr int WIN = TY + 8;                      // potential rows yb-4 .. yb+TY+3
+    static constexpr int NRING = 2 * TY;                    // ring cells per block
     static constexpr int K = 4;                             // outputs per explicit-window item
-    static constexpr int NSX = (CW + K - 1) / K;            // explicit x items per row
-    static constexpr int NSEGX = 8;                         // recursive x segments per row
-    static constexpr int SX = (CW + NSEGX - 1) / NSEGX;     // outputs per recursive segment
-    static constexpr int XSPAN = NSEGX * SX > NSX * K ? NSEGX * SX : NSX * K;
-    static constexpr int RW = (XSPAN + 2 * R) | 1;          // x-bar pitch (odd: spreads LDS banks)
-    static constexpr int RING_D = RING * CW;
+    static constexpr int NSEG = 8, SEG = BX / NSEG;         // recursive x segments per row, width
+    static constexpr int RW = (CW + 2 * R) | 1;             // x-bar pitch (odd: spreads LDS banks)
+    static constexpr int NU = FORCE == FORCE_HYBRID ? 2 : 1;  // operands per difference
     static constexpr int BAR_D = TY * RW;
+    static constexpr int PART_D = TY * BX;                  // one [TY][64] partial-sum array
+    static constexpr int FRING_D = (NRING * Q * (int)sizeof(Real) + 7) / 8;
     static constexpr int POST_D = (Q * PR * CW * (int)sizeof(Real) + 7) / 8;
-    static constexpr int DOUBLES = RING_D + BAR_D + 2 * NCELL + POST_D;
-    static constexpr int XBASE = 2 * BX;                    // x items run on wavefronts 2 and 3
-    static_assert(CW <= XBASE, "y items must fit below the x items");
-    static_assert(NCELL >= NT / 2, "block too small for the thread layout");
+    static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue staging
+    static constexpr int SCR_D = POST_D > WARM_ROWS * CW ? (POST_D > WSUM_ROWS * CW ? POST_D : WSUM_ROWS * CW)
+                                                         : (WARM_ROWS * CW > WSUM_ROWS * CW ? WARM_ROWS * CW
+                                                                                           : WSUM_ROWS * CW);
+    static constexpr int DOUBLES = BAR_D + 2 * NU * PART_D + PART_D + FRING_D + SCR_D;
+    static constexpr int XBASE = 2 * BX;                    // first x lane
+    static_assert(NI >= 1 && NI * NT == TY * BX, "block rows must fill the workgroup");
+    static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
+    static_assert(2 * TY * NSEG <= NT - XBASE && TY * (BX / K) <= NT - XBASE, "x lanes must fit");
+    static_assert(NRING * Q <= NT, "ring-cell loads: one value per thread");
 };
 
 template <typename Real, int FORCE, int TY>
 __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     constexpr int R = Radius<Real>::value;
-    using M = MarchShape<Real, TY, R>;
-    constexpr int CW = M::CW, RING = M::RING, PR = M::PR, RW = M::RW, NCELL = M::NCELL;
+    using M = MarchShape<Real, FORCE, TY, R>;
+    constexpr int CW = M::CW, PR = M::PR, RW = M::RW, NB = M::NB, WIN = M::WIN, SEG = M::SEG;
+    constexpr bool HYB = FORCE == FORCE_HYBRID;
     __shared__ double sm[M::DOUBLES];
-    double* ring = sm;                 // [RING][CW] phi rows, row y in slot rslot(y)
-    double* bar = ring + M::RING_D;    // [TY][RW]   phi of the block rows, x0-1-R .. x0+64+R (+ padding)
-    double* Fx = bar + M::BAR_D;       // [TY][CW]
-    double* Fy = Fx + NCELL;           // [TY][CW]
-    Real* post = reinterpret_cast<Real*>(Fy + NCELL);  // [Q][PR][CW], row y in slot pslot(y)
+    double* bar = sm;                          // [TY][RW] phi of the block rows, x0-1-R .. x0+64+R
+    double* Lx = bar + M::BAR_D;               // [TY][64] forward x sums (or the explicit d/dx)
+    double* Qx = Lx + M::PART_D;               // [TY][64] backward x sums
+    double* Lxu = Qx + M::PART_D;              // hybrid: the same for U = phi |phi|
+    double* Qxu = Lxu + (HYB ? M::PART_D : 0);
+    double* Fy = Qxu + (HYB ? M::PART_D : 0);  // [TY][64] y force of the interior
+    Real* fring = reinterpret_cast<Real*>(Fy + M::PART_D);                  // [2TY][Q] ring-cell f
+    double* scr = Fy + M::PART_D + M::FRING_D;                              // prologue staging
+    Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CW]
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (BX - 1), wave = tid >> 6;
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int chunk = t / nxb, strip = t - chunk * nxb;
@@ -76,50 +98,145 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     const int yb0 = ys - 1;
     const int nblk = (ye - ys + 2 + TY - 1) / TY;
 
-    // Ring slots of virtual rows (the smallest row read is ys - 1 - R, the
-    // smallest post-collision row ys - 3, so both arguments are >= 0).
-    auto rslot = [&](int y) { return (int)((unsigned)(y - ys + R + 8) % (unsigned)RING); };
+    // Every row index used below lies in [ys - R - 2, ye + (NB + 2) TY + 4],
+    // within one period of [0, ny) (ny > 2R + 1): one correction wraps it.
+    auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
     auto pslot = [&](int y) { return (int)((unsigned)(y - ys + 3) % (unsigned)PR); };
-    auto phi_at = [&](int y, int x) { return a.phi_in[(long)wrap(y, ny) * pitch + wrap(x, nx)]; };
+    auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
+    auto opu = [](double v) { return v * fabs(v); };
+    const double rr = a.rr, rr3 = a.rr3, rr4 = a.rr4, rd1 = a.rd1, rd2 = a.rd2, rK = a.rK;
 
-    // Loads of block yn (issued one block ahead) and their commit to LDS.
-    StageRegs<TY * CW> sring;  // phi rows yn+R .. yn+R+TY-1 (entering the ring)
-    StageRegs<TY * RW> sbar;   // x bar of rows yn .. yn+TY-1
-    Real fn[M::NC][Q];         // populations of the next block's collision cells
-    Real fc[M::NC][Q];         // populations of this block's collision cells
-    auto issue = [&](int yn) {
-        stage_issue(sring, [&](int i) {
-            const int r = i / CW, c = i - r * CW;
-            return phi_at(yn + R + r, x0 - 1 + c);
-        });
+    // Column owned by this lane (waves 0-1): interior column x0+lane, or the
+    // ring column of ring lane e = lane (x0-1 for e < TY, x0+64 otherwise).
+    const bool colw = wave < 2;
+    const int ccol = wave == 0 ? lane + 1 : (lane < TY ? 0 : CW - 1);   // collision column
+    const long xcol = wrap(x0 - 1 + ccol, nx);
+    const int rrow = lane % TY;                                           // ring lane's row
+    // Interior cell of this thread (collision and streaming): row tid / 64, column lane.
+    const long xin = wrap(x0 + lane, nx);
+
+    // ---------------------------------------------------------------- state
+    double win[WIN];                  // phi of rows yb-4 .. yb+TY+3, this lane's column
+    double W[NB], Wu[NB];             // block sums W_1 .. W_NB
+    double uprev = 0.0, uprevu = 0.0; // operand of the row preceding the next far rows
+    double l = 0.0, lu = 0.0;         // forward y state
+    double pnear[TY], pfar[TY];       // loads of the next block's column rows
+    StageRegs<TY * RW> sbar;          // loads of the next block's x bar
+    double fr = 0.0;                  // one ring-cell population (tid < 2 TY Q)
+    Real fc[M::NI][Q];                // interior populations (loaded one phase 4 ahead)
+
+    auto issue = [&](int yn) {        // potential and ring-cell loads of block yn
         stage_issue(sbar, [&](int i) {
             const int r = i / RW, c = i - r * RW;
-            return phi_at(yn + r, x0 - 1 - R + c);
+            return a.phi_in[(long)wrapy(yn + r) * pitch + wrap(x0 - 1 - R + c, nx)];
         });
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < M::NC; ++i) {
-            const int c = min(tid + i * NT, NCELL - 1);  // past the end: a duplicate, never used
-            const int r = c / CW, cc = c - r * CW;
-            const int xw = wrap(x0 - 1 + cc, nx), yw = wrap(yn + r, ny);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) fn[i][q] = a.f_in[fidx(xw, yw, q, nxb)];
+        if (tid < M::NRING * Q) {
+            const int e = tid / Q, q = tid - e * Q;
+            const int xr = wrap(e < TY ? x0 - 1 : x0 + BX, nx);
+            fr = (double)a.f_in[fidx(xr, wrapy(yn + e % TY), q, nxb)];
         }
-        __builtin_amdgcn_sched_barrier(0);
     };
-    auto commit = [&](int yn) {
+    // The interior populations and the new state are touched once per step:
+    // non-temporal accesses keep them from evicting the potential rows, which
+    // are read again a few blocks later.
+    auto issue_f = [&](int yn) {      // interior populations of block yn (after their last use)
 #pragma unroll
-        for (int j = 0; j < StageRegs<TY * CW>::PER; ++j) {
-            const int i = tid + j * NT;
-            if (i < TY * CW) {
-                const int r = i / CW, c = i - r * CW;
-                ring[rslot(yn + R + r) * CW + c] = sring.v[j];
+        for (int i = 0; i < M::NI; ++i) {
+            const int yw = wrapy(yn + (tid >> 6) + i * (NT / BX));
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fc[i][q] = __builtin_nontemporal_load(a.f_in + fidx((int)xin, yw, q, nxb));
+        }
+    };
+    auto issue_col = [&](int yn) {    // new window rows yn+4 .. and far rows of block yn
+        if (colw) {
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                pnear[j] = a.phi_in[(long)wrapy(yn + 4 + j) * pitch + xcol];
+                pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
             }
         }
-        stage_commit(bar, sbar);
     };
-    // Rows ylo .. ylo+nrows-1 into the ring (chunk prologue only).
-    auto ring_fill = [&](int ylo, int nrows) {
+    // New block sum from the operands of rows uprev, p[0 .. TY-1]:
+    // t_n = r^4 (u_{n+1} - u_n) over that row sequence, W = sum r^n t_n.
+    auto block_sum = [&](double u0, const double (&p)[TY], bool hyb) {
+        double w = 0.0;
+#pragma unroll
+        for (int n = TY - 1; n >= 0; --n) {
+            const double un1 = hyb ? opu(p[n]) : op(p[n]);
+            const double un = n == 0 ? u0 : (hyb ? opu(p[n - 1]) : op(p[n - 1]));
+            w = fma(rr, w, rr4 * (un1 - un));
+        }
+        return w;
+    };
+    auto commit_col = [&]() {         // advance the column windows by one block
+        if (colw) {
+#pragma unroll
+            for (int j = 0; j < WIN - TY; ++j) win[j] = win[j + TY];
+#pragma unroll
+            for (int j = 0; j < TY; ++j) win[WIN - TY + j] = pnear[j];
+#pragma unroll
+            for (int j = 0; j < NB - 1; ++j) W[j] = W[j + 1];
+            W[NB - 1] = block_sum(uprev, pfar, false);
+            uprev = op(pfar[TY - 1]);
+            if (HYB) {
+#pragma unroll
+                for (int j = 0; j < NB - 1; ++j) Wu[j] = Wu[j + 1];
+                Wu[NB - 1] = block_sum(uprevu, pfar, true);
+                uprevu = opu(pfar[TY - 1]);
+            }
+        }
+    };
+    auto commit = [&]() {             // the next block's bar and ring cells into LDS
+        stage_commit(bar, sbar);
+        if (tid < M::NRING * Q) fring[tid] = (Real)fr;
+    };
+
+    // d/dy of this lane's column over the block rows from its windows (lane
+    // state only): g[o], gu[o] for rows yb+o.  Advances the forward state.
+    // Window index of row y: y - (yb - 4).
+    double rT = 1.0;  // r^TY
+#pragma unroll
+    for (int j = 0; j < TY; ++j) rT *= rr;
+    auto ddy = [&](double (&g)[TY], double (&gu)[TY]) {
+        double Lt[TY], Ltu[TY];
+#pragma unroll
+        for (int o = 0; o < TY; ++o) {  // forward update at row yb+o-1 reads rows yb+o-3, yb+o-4
+            l = fma(rr, l, rr4 * (op(win[o + 1]) - op(win[o])));
+            Lt[o] = l;
+            if (HYB) {
+                lu = fma(rr, lu, rr4 * (opu(win[o + 1]) - opu(win[o])));
+                Ltu[o] = lu;
+            }
+        }
+        double q = W[NB - 1], qu = HYB ? Wu[NB - 1] : 0.0;  // q(yb+1+TY), Horner over the block sums
+#pragma unroll
+        for (int j = NB - 2; j >= 0; --j) {
+            q = fma(rT, q, W[j]);
+            if (HYB) qu = fma(rT, qu, Wu[j]);
+        }
+#pragma unroll
+        for (int o = TY - 1; o >= 0; --o) {
+            // q(yb+o+1) = t_{yb+o+1} + r q(yb+o+2), t_i from rows i+3, i+2
+            q = fma(rr, q, rr4 * (op(win[o + 8]) - op(win[o + 7])));
+            const int w = o + 4;
+            g[o] = rd1 * (op(win[w + 1]) - op(win[w - 1])) + rd2 * (op(win[w + 2]) - op(win[w - 2])) +
+                   rK * (rr3 * (op(win[w + 3]) - op(win[w - 3])) + q + Lt[o]);
+            if (HYB) {
+                qu = fma(rr, qu, rr4 * (opu(win[o + 8]) - opu(win[o + 7])));
+                gu[o] = rd1 * (opu(win[w + 1]) - opu(win[w - 1])) + rd2 * (opu(win[w + 2]) - opu(win[w - 2])) +
+                        rK * (rr3 * (opu(win[w + 3]) - opu(win[w - 3])) + qu + Ltu[o]);
+            } else {
+                gu[o] = 0.0;
+            }
+        }
+    };
+
+    // ------------------------------------------------------------- prologue
+    // Forward y state up to the first block (updates at rows yb0-(R-3) ..
+    // yb0-2 read rows yb0-R .. yb0-4), the block sums W_1 .. W_NB of block 0
+    // (rows yb0+3+TY .. yb0+3+(NB+1)TY) and the window (rows yb0-4 ..
+    // yb0+TY+3); rows are staged in the post-collision area.
+    auto stage_rows = [&](int ylo, int nrows) {
         const int n = nrows * CW;
         for (int i0 = 0; i0 < n; i0 += 8 * NT) {
             double v[8];
@@ -127,174 +244,226 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
             for (int j = 0; j < 8; ++j) {
                 const int i = min(i0 + tid + j * NT, n - 1);
                 const int r = i / CW, c = i - r * CW;
-                v[j] = phi_at(ylo + r, x0 - 1 + c);
+                v[j] = a.phi_in[(long)wrapy(ylo + r) * pitch + wrap(x0 - 1 + c, nx)];
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int i = i0 + tid + j * NT;
-                if (i < n) {
-                    const int r = i / CW, c = i - r * CW;
-                    ring[rslot(ylo + r) * CW + c] = v[j];
-                }
+                if (i < n) scr[i] = v[j];
             }
         }
     };
-
-    auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
-    auto opu = [](double v) { return v * fabs(v); };
-    const double rr = a.rr, rr3 = a.rr3, rr4 = a.rr4, rd1 = a.rd1, rd2 = a.rd2, rK = a.rK;
-
-    // Prologue: the forward y recursion up to the first block (updates at rows
-    // yb0-(R-3) .. yb0-2 read rows yb0-R .. yb0-4), then the ring for block 0.
-    double l = 0.0, lu = 0.0;  // forward state of column tid (tid < CW)
-    ring_fill(yb0 - R, R - 3);
+    if (colw) {
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) win[j] = a.phi_in[(long)wrapy(yb0 - 4 + j) * pitch + xcol];
+    }
+    stage_rows(yb0 - R, M::WARM_ROWS);
     __syncthreads();
-    if (tid < CW) {
-        const double* colp = ring + tid;
-        for (int i = yb0 - (R - 3); i <= yb0 - 2; ++i) {
-            const double v2 = colp[rslot(i - 2) * CW], v3 = colp[rslot(i - 3) * CW];
+    if (colw) {
+        for (int m = 1; m <= R - 4; ++m) {
+            const double v2 = scr[m * CW + ccol], v3 = scr[(m - 1) * CW + ccol];
             l = fma(rr, l, rr4 * (op(v2) - op(v3)));
-            if (FORCE == FORCE_HYBRID) lu = fma(rr, lu, rr4 * (opu(v2) - opu(v3)));
+            if (HYB) lu = fma(rr, lu, rr4 * (opu(v2) - opu(v3)));
         }
     }
     __syncthreads();
-    ring_fill(yb0 - 4, R + 4);
+    stage_rows(yb0 + 3 + TY, M::WSUM_ROWS);
+    __syncthreads();
+    if (colw) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double p[TY];
+#pragma unroll
+            for (int n = 0; n < TY; ++n) p[n] = scr[(j * TY + n + 1) * CW + ccol];
+            const double s0 = scr[j * TY * CW + ccol];
+            W[j] = block_sum(op(s0), p, false);
+            if (HYB) Wu[j] = block_sum(opu(s0), p, true);
+        }
+        const double last = scr[NB * TY * CW + ccol];
+        uprev = op(last);
+        uprevu = opu(last);
+    }
+    __syncthreads();
     issue(yb0);
-    commit(yb0);
-#pragma unroll
-    for (int i = 0; i < M::NC; ++i)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) fc[i][q] = fn[i][q];
+    issue_f(yb0);
+    commit();
     __syncthreads();
 
+    // ------------------------------------------------------------ the march
     for (int k = 0; k < nblk; ++k) {
         const int yb = yb0 + k * TY;
         const bool more = k + 1 < nblk;
-        if (more) issue(yb + TY);
-
-        // Phase 2: forces of the block's collision cells.
-        if (tid < CW) {
-            // d/dy of column tid over rows yb .. yb+TY-1; ring row yb-4+j at ring_row(j).
-            const double* colp = ring + tid;
-            const int sb = rslot(yb - 4);
-            auto at = [&](int j) {
-                const int s = sb + j;
-                return colp[(s >= RING ? s - RING : s) * CW];
-            };
-            double Lt[TY], Ltu[TY];
-#pragma unroll
-            for (int j = 0; j < TY; ++j) {  // update at row yb-1+j reads rows yb-3+j, yb-4+j
-                const double v2 = at(j + 1), v3 = at(j);
-                l = fma(rr, l, rr4 * (op(v2) - op(v3)));
-                if (FORCE == FORCE_HYBRID) lu = fma(rr, lu, rr4 * (opu(v2) - opu(v3)));
-                Lt[j] = l;
-                Ltu[j] = lu;
-            }
-            double qv = 0.0, qu = 0.0;
-#pragma unroll
-            for (int i = TY - 1 + (R - 3); i >= 1; --i) {  // update at row yb+i reads rows yb+i+3, yb+i+2
-                const double v3 = at(i + 7), v2 = at(i + 6);
-                qv = fma(rr, qv, rr4 * (op(v3) - op(v2)));
-                if (FORCE == FORCE_HYBRID) qu = fma(rr, qu, rr4 * (opu(v3) - opu(v2)));
-                const int o = i - 1;  // output row yb+o
-                if (o < TY) {
-                    const double a1 = at(o + 5), b1 = at(o + 3), a2 = at(o + 6), b2 = at(o + 2);
-                    const double a3 = at(o + 7), b3 = at(o + 1);
-                    const double g = rd1 * (op(a1) - op(b1)) + rd2 * (op(a2) - op(b2)) +
-                                     rK * (rr3 * (op(a3) - op(b3)) + qv + Lt[o]);
-                    double gu = 0.0;
-                    if (FORCE == FORCE_HYBRID)
-                        gu = rd1 * (opu(a1) - opu(b1)) + rd2 * (opu(a2) - opu(b2)) +
-                             rK * (rr3 * (opu(a3) - opu(b3)) + qu + Ltu[o]);
-                    Fy[o * CW + tid] = force_from<FORCE>(at(o + 4), g, gu, a.A);
-                }
-            }
-        } else if (tid >= M::XBASE) {
-            // d/dx of the block rows from the bar.
-            if (a.rec_x) {
-                for (int it = tid - M::XBASE; it < TY * M::NSEGX; it += NT - M::XBASE) {
-                    const int r = it % TY, s = it / TY;
-                    double out[M::SX], outu[M::SX];
-                    stencil_recursive<FORCE, M::SX, R>(bar + r * RW + R + s * M::SX, 1, rr, rr3, rr4, rd1, rd2, rK, out,
-                                                       outu);
-#pragma unroll
-                    for (int j = 0; j < M::SX; ++j) {
-                        const int cx = s * M::SX + j;
-                        if (cx < CW) Fx[r * CW + cx] = force_from<FORCE>(bar[r * RW + cx + R], out[j], outu[j], a.A);
-                    }
-                }
-            } else {
-                for (int it = tid - M::XBASE; it < TY * M::NSX; it += NT - M::XBASE) {
-                    const int r = it % TY, s = it / TY;
-                    double acc[M::K], accu[M::K];
-                    stencil_window<FORCE, M::K, R>(bar + r * RW + s * M::K, 1, a.tx_tab, acc, accu);
-#pragma unroll
-                    for (int j = 0; j < M::K; ++j) {
-                        const int cx = s * M::K + j;
-                        if (cx < CW) Fx[r * CW + cx] = force_from<FORCE>(bar[r * RW + cx + R], acc[j], accu[j], a.A);
-                    }
-                }
-            }
+        if (more) {
+            issue_col(yb + TY);
+            issue(yb + TY);
         }
-        __syncthreads();
 
-        // Phase 3: collision of the block into the post-collision ring.
+        // Phase 2: forces; the ring cells are also collided here.
+        if (wave == 0) {
+            double g[TY], gu[TY];
+            ddy(g, gu);
 #pragma unroll
-        for (int i = 0; i < M::NC; ++i) {
-            const int c = tid + i * NT;
-            if (c < NCELL) {
-                const int r = c / CW, cc = c - r * CW;
-                double g[Q];
+            for (int o = 0; o < TY; ++o) Fy[o * BX + lane] = force_from<FORCE>(win[o + 4], g[o], gu[o], a.A);
+        } else if (wave == 1) {
+            double g[TY], gu[TY];
+            ddy(g, gu);
+            if (lane < M::NRING) {
+                double gy = 0.0, gyu = 0.0, phic = 0.0;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) g[q] = (double)fc[i][q];
+                for (int o = 0; o < TY; ++o)
+                    if (o == rrow) {
+                        gy = g[o];
+                        gyu = gu[o];
+                        phic = win[o + 4];
+                    }
+                // explicit d/dx of the ring cell over the bar (sign-folded table)
+                const double* br = bar + rrow * RW + ccol + R;
+                double sx[4] = {0.0, 0.0, 0.0, 0.0}, sxu[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums
+#pragma unroll 8
+                for (int n = 1; n <= R; ++n) {
+                    const double c = a.tx_tab[TAB_OFF + n];
+                    const double vp = br[n], vm = br[-n];
+                    sx[n & 3] = fma(c, op(vp) - op(vm), sx[n & 3]);
+                    if (HYB) sxu[n & 3] = fma(c, opu(vp) - opu(vm), sxu[n & 3]);
+                }
+                const double gx = (sx[0] + sx[1]) + (sx[2] + sx[3]);
+                const double gxu = (sxu[0] + sxu[1]) + (sxu[2] + sxu[3]);
+                const double Fxr = force_from<FORCE>(phic, gx, gxu, a.A);
+                const double Fyr = force_from<FORCE>(phic, gy, gyu, a.A);
+                double g9[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) g9[q] = (double)fring[lane * Q + q];
                 double rho, jx, jy;
-                moments(g, rho, jx, jy);
-                collide(g, rho, jx, jy, Fx[c], Fy[c], a.omega);
-                const int ps = pslot(yb + r);
+                moments(g9, rho, jx, jy);
+                collide(g9, rho, jx, jy, Fxr, Fyr, a.omega);
+                const int ps = pslot(yb + rrow);
 #pragma unroll
-                for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CW + cc] = (Real)g[q];
+                for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CW + ccol] = (Real)g9[q];
+            }
+        } else if (a.rec_x) {
+            // forward (even lane) and backward (odd lane) x recursion of one
+            // 8-column segment of one row, in lockstep: at step j both read
+            // u[pa] - u[pa - 1], pa = A0 + S j; the last SEG steps give the
+            // outputs o = B0 + S j, kept in registers and stored after the loop
+            // (no LDS store inside the loop, so its loads can run ahead).
+            const int xi = tid - M::XBASE;
+            if (xi < 2 * TY * M::NSEG) {
+                const int item = xi >> 1, dir = xi & 1;
+                const int r = item % TY, sg = item / TY;
+                const double* base = bar + r * RW + R + 1 + sg * SEG;  // interior column 1 + sg SEG at k = 0
+                const int A0 = dir ? SEG + R - 1 : -(R - 1), S = dir ? -1 : 1;
+                double acc = 0.0, accu = 0.0, out[SEG], outu[SEG];
+#pragma unroll 8
+                for (int j = 0; j < R - 4; ++j) {  // warm-up steps
+                    const int pa = A0 + S * j;
+                    const double va = base[pa], vb = base[pa - 1];
+                    acc = fma(rr, acc, rr4 * (op(va) - op(vb)));
+                    if (HYB) accu = fma(rr, accu, rr4 * (opu(va) - opu(vb)));
+                }
+#pragma unroll
+                for (int m = 0; m < SEG; ++m) {    // output steps
+                    const int pa = A0 + S * (R - 4 + m);
+                    const double va = base[pa], vb = base[pa - 1];
+                    acc = fma(rr, acc, rr4 * (op(va) - op(vb)));
+                    if (HYB) accu = fma(rr, accu, rr4 * (opu(va) - opu(vb)));
+                    out[m] = acc;
+                    outu[m] = accu;
+                }
+                // step j = R-4+m gives output o = m (forward) or SEG-1-m (backward)
+                double* dst = (dir ? Qx : Lx) + r * BX + sg * SEG;
+                double* dstu = (dir ? Qxu : Lxu) + r * BX + sg * SEG;
+#pragma unroll
+                for (int m = 0; m < SEG; ++m) {
+                    const int o = dir ? SEG - 1 - m : m;
+                    dst[o] = out[m];
+                    if (HYB) dstu[o] = outu[m];
+                }
+            }
+        } else {
+            // short x axis: the explicit periodic row, K outputs per lane
+            const int xi = tid - M::XBASE;
+            if (xi < TY * (BX / M::K)) {
+                const int r = xi % TY, sg = xi / TY;
+                double acc[M::K], accu[M::K];
+                stencil_window<FORCE, M::K, R>(bar + r * RW + 1 + sg * M::K, 1, a.tx_tab, acc, accu);
+#pragma unroll
+                for (int j = 0; j < M::K; ++j) {
+                    Lx[r * BX + sg * M::K + j] = acc[j];
+                    if (HYB) Lxu[r * BX + sg * M::K + j] = accu[j];
+                }
             }
         }
         __syncthreads();
 
-        // Phase 4: pull streaming of rows yb-1 .. yb+TY-2 and phi_{t+1}.
+        // Phase 3: collision of the interior cells.
 #pragma unroll
         for (int i = 0; i < M::NI; ++i) {
             const int c = tid + i * NT;
-            if (c < TY * BX) {
-                const int r = c / BX, lx = c - r * BX;
-                const int y = yb - 1 + r, x = x0 + lx;
-                if (y >= ys && y < ye && x < nx) {
-                    double g[Q];
+            const int r = c >> 6, cc = lane + 1;
+            const double* br = bar + r * RW + cc + R;
+            double gx, gxu = 0.0;
+            if (a.rec_x) {
+                gx = rd1 * (op(br[1]) - op(br[-1])) + rd2 * (op(br[2]) - op(br[-2])) +
+                     rK * (rr3 * (op(br[3]) - op(br[-3])) + Qx[c] + Lx[c]);
+                if (HYB)
+                    gxu = rd1 * (opu(br[1]) - opu(br[-1])) + rd2 * (opu(br[2]) - opu(br[-2])) +
+                          rK * (rr3 * (opu(br[3]) - opu(br[-3])) + Qxu[c] + Lxu[c]);
+            } else {
+                gx = Lx[c];
+                if (HYB) gxu = Lxu[c];
+            }
+            const double Fxc = force_from<FORCE>(br[0], gx, gxu, a.A);
+            double g[Q];
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        const Real v = post[(q * PR + pslot(y - ey(q))) * CW + lx + 1 - ex(q)];
-                        a.f_out[fidx(x, y, q, nxb)] = v;
-                        g[q] = (double)v;
-                    }
-                    double rho, jx, jy;
-                    moments(g, rho, jx, jy);
-                    a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, rho));
+            for (int q = 0; q < Q; ++q) g[q] = (double)fc[i][q];
+            double rho, jx, jy;
+            moments(g, rho, jx, jy);
+            collide(g, rho, jx, jy, Fxc, Fy[c], a.omega);
+            const int ps = pslot(yb + r);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CW + cc] = (Real)g[q];
+        }
+        __syncthreads();
+
+        // Phase 4: pull streaming of rows yb-1 .. yb+TY-2 and phi_{t+1}; the
+        // populations of the next block are loaded meanwhile.
+        if (more) issue_f(yb + TY);
+#pragma unroll
+        for (int i = 0; i < M::NI; ++i) {
+            const int c = tid + i * NT;
+            const int r = c >> 6;
+            const int y = yb - 1 + r, x = x0 + lane;
+            if (y >= ys && y < ye && x < nx) {
+                double g[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const Real v = post[(q * PR + pslot(y - ey(q))) * CW + lane + 1 - ex(q)];
+                    __builtin_nontemporal_store(v, a.f_out + fidx(x, y, q, nxb));
+                    g[q] = (double)v;
                 }
+                double rho, jx, jy;
+                moments(g, rho, jx, jy);
+                __builtin_nontemporal_store(phi_of<FORCE>(potential(a.eos, rho)), a.phi_out + (long)y * pitch + x);
             }
         }
 
-        // Phase 5: the next block's potential rows into LDS.
+        // Phase 5: the loads of step 1 into LDS and the column windows.
         if (more) {
-            commit(yb + TY);
-#pragma unroll
-            for (int i = 0; i < M::NC; ++i)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) fc[i][q] = fn[i][q];
+            commit();
+            commit_col();
         }
         __syncthreads();
     }
 }
 
-// LDS bytes of one workgroup of the marching kernel.
-template <typename Real, int TY>
-constexpr int march_lds_bytes() {
-    return MarchShape<Real, TY, Radius<Real>::value>::DOUBLES * 8;
+// Rows per block and chunking constraints of the marching kernel: every row
+// it touches must lie within one period of the chunk (ny > (NB + 2) TY + 3)
+// besides the geometric form along y (ny > 2R + 1).
+template <typename Real>
+inline bool march_fits(int ny, int ty) {
+    constexpr int R = Radius<Real>::value;
+    const int nb = (R - 3 + ty - 1) / ty;
+    return ny > 2 * R + 1 && ny > (nb + 2) * ty + 3;
 }
 
 // Launch over nchunk y chunks of every 64-column strip (nchunk in [1, ny]).
