@@ -42,20 +42,35 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+_WORKLOADS = {}
+
+
 def workload(name: str, seed: int = 2024):
-    """(params kwargs, rho0, ux0, uy0, description) of a named workload."""
+    """(params, rho0, ux0, uy0, description) of a named workload (inputs cached
+    per process; the params object is a fresh copy)."""
+    import copy
+    key = (name, seed)
+    if key not in _WORKLOADS:
+        _WORKLOADS[key] = _make_workload(name, seed)
+    p, rho0, ux0, uy0, desc = _WORKLOADS[key]
+    return copy.copy(p), rho0, ux0, uy0, desc
+
+
+def _make_workload(name: str, seed: int):
     import paper_1712_06079_amd as L
-    if name == "c5":
-        n = 4096
+    if name in ("c5", "c5_2048", "c5_8192"):
+        # the large dynamic case; the other sizes keep its droplet density
+        n = {"c5": 4096, "c5_2048": 2048, "c5_8192": 8192}[name]
+        ndrop = 400 * n * n // (4096 * 4096)
         p = L.Params(nx=n, ny=n, eos="cs", force="sc", a=1.0, b=4.0, R=1.0, k=0.04, tau=1.0)
         tc, _ = L.critical(p)
         p.T = 0.5 * tc
         rv, rl, _ = L.maxwell(p, p.T)
-        cx, cy, rr = I.place_droplets(n, n, 400, 10.0, 60.0, 4.0, seed=seed)
+        cx, cy, rr = I.place_droplets(n, n, ndrop, 10.0, 60.0, 4.0, seed=seed)
         rho0 = I.droplets(n, n, rv, rl, cx, cy, rr, 4.0)
         ux0 = I.gaussian((n, n), 1e-3, seed=seed + 1)
         uy0 = I.gaussian((n, n), 1e-3, seed=seed + 2)
-        desc = "4096x4096 CS T=0.5Tc SC+HDM, 400 droplets R~U[10,60], u noise 1e-3"
+        desc = f"{n}x{n} CS T=0.5Tc SC+HDM, {ndrop} droplets R~U[10,60], u noise 1e-3"
         return p, rho0, ux0, uy0, desc
     if name == "c2":
         n = 1024
@@ -260,26 +275,138 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
     }
 
 
-def copy_probe(gib: float = 2.0, reps: int = 20):
-    """A plain streaming kernel of known size (dst = 1.0 * src, FP64): reads and
-    writes `gib` GiB per launch.  Its rocprofv3 FETCH_SIZE / WRITE_SIZE give the
-    counter-to-bytes scale, and its rate the attainable HBM bandwidth."""
+def copy_probe(gib: float = 2.0, reps: int = 20, kinds=("mul",)):
+    """Plain streaming kernels of known size (FP64, `gib` GiB read and written
+    per launch): "mul" is dst = 1.0 * src (the kernel the counter calibration
+    uses), "copy" is dst.copy_(src).  Their rates are the attainable HBM
+    bandwidth the fused step is compared with."""
     import torch
     n = int(gib * (1 << 30) / 8)
     src = torch.rand(n, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        torch.mul(src, 1.0, out=dst)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        torch.mul(src, 1.0, out=dst)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    moved = 2 * n * 8
-    return {"bytes_per_launch": moved, "ms": ms, "GBps": moved / (ms * 1e-3) / 1e9}
+    ops = {"mul": lambda: torch.mul(src, 1.0, out=dst), "copy": lambda: dst.copy_(src)}
+    out = {}
+    for kind in kinds:
+        f = ops[kind]
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = 2 * n * 8
+        out[kind] = {"bytes_per_launch": moved, "ms": round(ms, 4), "GBps": round(moved / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+def _domain(name: str, prec: str):
+    import torch
+
+    import paper_1712_06079_amd as L
+    p, rho0, ux0, uy0, desc = workload(name)
+    p.prec = prec
+    t = lambda a: None if a is None else torch.from_numpy(a).to("cuda:0")  # noqa: E731
+    return L.Domain(p, t(rho0), t(ux0), t(uy0)), p, desc
+
+
+def _timed_steps(d, steps: int, label: str, chunk: int = 5000):
+    """Run `steps` steps in chunks (progress on stderr); GPU time in ms."""
+    import torch
+    ms = 0.0
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        d.step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += k
+        print(f"[bench] {label}: {done}/{steps} steps", file=sys.stderr, flush=True)
+    return ms
+
+
+def droplet_report(steps: int):
+    """The single large droplet (1024^2 CS T=0.6Tc ZC+HDM, R=128, W=4) in both
+    population precisions: MLUPS, max |v|, the Laplace pressure jump
+    dp = p(centre) - p(corner) with p = rho/3 + U, the effective radius from
+    the area inside rho = (rho_l + rho_v)/2 and sigma_L = dp R_eff."""
+    import numpy as np
+
+    import paper_1712_06079_amd as L
+    out = {}
+    for prec in ("f64", "f32"):
+        d, p, desc = _domain("c2", prec)
+        rv, rl, _ = L.maxwell(p, p.T)
+        ms = _timed_steps(d, steps, f"c2 {prec}")
+        m = {k: v.cpu().numpy() for k, v in d.moments().items()}
+        n = p.nx
+        rho, pr = m["rho"], m["p"]
+        area = float(np.count_nonzero(rho > 0.5 * (rl + rv)))
+        reff = (area / np.pi) ** 0.5
+        dp = float(pr[n // 2, n // 2] - pr[0, 0])
+        es = 8 if prec == "f64" else 4
+        mlups = n * n * steps / (ms * 1e-3) / 1e6
+        out[prec] = {"steps": steps, "mlups": round(mlups, 1),
+                     "roofline_frac": round(mlups * 1e6 * 2 * Q * es / (HBM_PEAK_GBS * 1e9), 4),
+                     "max_v": float(m["totals"][3]), "dp": dp, "R_eff": round(reff, 3), "sigma_L": dp * reff,
+                     "mass": float(m["totals"][0]), "finite": d.check_finite()}
+        print(f"[bench] c2 {prec}: {mlups:.0f} MLUPS, max|v| {out[prec]['max_v']:.3e}, dp {dp:.4e}, "
+              f"R_eff {reff:.2f}, sigma_L {dp * reff:.4e}", file=sys.stderr, flush=True)
+        del d
+    out["note"] = "1024^2: 168 MB of FP64 state, resident in the 256 MB Infinity Cache (not an HBM roofline case)"
+    out["desc"] = desc
+    return out
+
+
+def long_run_comparison(steps: int):
+    """The large dynamic case run `steps` steps with FP64 and with FP32
+    populations: MLUPS of each, the relative difference of the final mass and
+    the L1 distance of the 256-bin density histograms on [0, 1.05 rho_l]."""
+    import numpy as np
+
+    import paper_1712_06079_amd as L
+    res, hist = {}, {}
+    for prec in ("f64", "f32"):
+        d, p, desc = _domain("c5", prec)
+        rv, rl, _ = L.maxwell(p, p.T)
+        ms = _timed_steps(d, steps, f"c5 long {prec}")
+        m = d.moments()
+        rho = m["rho"].cpu().numpy()
+        tot = m["totals"].cpu().numpy() if hasattr(m["totals"], "cpu") else m["totals"]
+        h, _ = np.histogram(rho, bins=256, range=(0.0, 1.05 * rl))
+        hist[prec] = h / rho.size
+        res[prec] = {"mlups": round(p.nx * p.ny * steps / (ms * 1e-3) / 1e6, 1), "mass": float(tot[0]),
+                     "max_v": float(tot[3]), "finite": d.check_finite(), "rho_max": float(rho.max()),
+                     "rho_min": float(rho.min())}
+        del d, m, rho
+    out = {"steps": steps, "desc": desc, "f64": res["f64"], "f32": res["f32"],
+           "mass_rel_diff": abs(res["f32"]["mass"] - res["f64"]["mass"]) / abs(res["f64"]["mass"]),
+           "hist_l1": float(np.abs(hist["f32"] - hist["f64"]).sum())}
+    print(f"[bench] c5 {steps} steps: f32-vs-f64 mass rel diff {out['mass_rel_diff']:.3e}, "
+          f"histogram L1 {out['hist_l1']:.3e}", file=sys.stderr, flush=True)
+    return out
+
+
+def size_curve(sizes, steps: int):
+    """MLUPS of the large dynamic recipe at other lattice sizes (FP64 and FP32)."""
+    out = []
+    for n in sizes:
+        for prec in ("f64", "f32"):
+            d, p, _ = _domain(f"c5_{n}", prec)
+            d.step(10)
+            ms = _timed_steps(d, steps, f"curve {n} {prec}", chunk=steps)
+            mlups = n * n * steps / (ms * 1e-3) / 1e6
+            es = 8 if prec == "f64" else 4
+            out.append({"n": n, "storage": prec, "mlups": round(mlups, 1),
+                        "roofline_frac": round(mlups * 1e6 * 2 * Q * es / (HBM_PEAK_GBS * 1e9), 4)})
+            del d
+    return out
 
 
 def cpu_baseline(name: str, sample_steps: int):
@@ -307,15 +434,21 @@ def main():
                     help="0 automatic (strip march here), 1 two-pass reference, 2 fused tiles, 3 fused strip march")
     ap.add_argument("--tile", type=int, default=0, help="rows per tile or marching block (0 = default)")
     ap.add_argument("--chunks", type=int, default=0, help="y chunks per strip of the marching kernel (0 = automatic)")
-    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle sample steps (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle sample steps (0 = skip)")
     ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-probe", action="store_true", help="only run the streaming-copy calibration kernel")
-    ap.add_argument("--batch-steps", type=int, default=2000, help="batched-sweep steps (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
+    ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
+    ap.add_argument("--long-steps", type=int, default=50000, help="FP32-vs-FP64 large-case steps (0 = skip)")
+    ap.add_argument("--curve-steps", type=int, default=200, help="steps per point of the size curve (0 = skip)")
     args = ap.parse_args()
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
+    if args.gpus > 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -345,6 +478,10 @@ def main():
         adjoint = adjoint_cost(args.adjoint_steps, 70)
         print(f"[bench] adjoint/forward step {adjoint['adjoint_over_forward']}, gradient/forward "
               f"{adjoint['gradient_over_forward']}", file=sys.stderr, flush=True)
+    droplet = droplet_report(args.droplet_steps) if args.droplet_steps > 0 else None
+    long_cmp = long_run_comparison(args.long_steps) if args.long_steps > 0 and args.workload == "c5" else None
+    curve = size_curve((2048, 8192), args.curve_steps) if args.curve_steps > 0 and args.workload == "c5" else None
+    probe = copy_probe(kinds=("mul", "copy")) if args.curve_steps > 0 else None
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
     kname = KERNEL_NAMES.get(args.variant, "k_march")
     traffic = traffic_from_profile(kname, args.workload, args.prec)
@@ -367,6 +504,14 @@ def main():
         line["batch"] = batch
     if adjoint:
         line["adjoint"] = adjoint
+    if droplet:
+        line["droplet_c2"] = droplet
+    if long_cmp:
+        line["long_run"] = long_cmp
+    if curve:
+        line["size_curve"] = curve
+    if probe:
+        line["copy_probe"] = probe
     print(json.dumps(line), flush=True)
 
 
