@@ -132,9 +132,9 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
     int& per_cu = ty == 4 ? d->march_occ[0] : d->march_occ[1];  // cached occupancy query
     if (per_cu == 0) {
         if (ty == 4)
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 4>, lbm::NT, 0));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 4, true>, lbm::NT, 0));
         else
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 8>, lbm::NT, 0));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 8, true>, lbm::NT, 0));
         if (per_cu < 1) per_cu = 1;
     }
     const long target = (long)d->ncu * per_cu;

@@ -31,13 +31,13 @@
 //           partial sums) and streaming.
 // Per block (collision rows yb .. yb+TY-1, yb = ys - 1 + k TY):
 //  1  issue the loads of block k+1 (ring-cell populations, x bar, the new
-//     potential rows of each column; its interior populations follow in 4);
+//     potential rows of each column); its interior populations follow in 4;
 //  2  forces (and the ring cells' collision);
 //  3  collision of the interior cells into the post-collision ring (rows
 //     yb-2 .. yb+TY-1);
-//  4  pull streaming of rows yb-1 .. yb+TY-2 (stored when inside [ys, ye)),
-//     then rho -> U -> phi_{t+1} of those cells;
-//  5  commit the loads of step 1 (LDS, register windows).
+//  4  commit the loads of step 1 (LDS, register windows), issue the next
+//     block's interior populations, then pull streaming of rows yb-1 ..
+//     yb+TY-2 (stored when inside [ys, ye)) and rho -> U -> phi_{t+1}.
 #pragma once
 
 #include "lbm_fused.hpp"
@@ -47,7 +47,9 @@ namespace lbm {
 template <typename Real, int FORCE, int TY, int R>
 struct MarchShape {
     static constexpr int CW = BX + 2;                       // collision columns x0-1 .. x0+64
-    static constexpr int NI = TY * BX / NT;                 // interior cells per thread
+    static constexpr int CWP = CW + 2;                      // post-collision row pitch (column cc at cc + 1)
+    static constexpr int NPAIR = TY * BX / 2;               // interior cell pairs (x, x+1) per block
+    static constexpr int NP = (NPAIR + NT - 1) / NT;        // pairs per thread
     static constexpr int PR = TY + 2;                       // post-collision rows yb-2 .. yb+TY-1
     static constexpr int NB = (R - 3 + TY - 1) / TY;        // block sums ahead (NB TY + 3 >= R)
     static constexpr int WIN = TY + 8;                      // potential rows yb-4 .. yb+TY+3
@@ -59,26 +61,32 @@ struct MarchShape {
     static constexpr int BAR_D = TY * RW;
     static constexpr int PART_D = TY * BX;                  // one [TY][64] partial-sum array
     static constexpr int FRING_D = (NRING * Q * (int)sizeof(Real) + 7) / 8;
-    static constexpr int POST_D = (Q * PR * CW * (int)sizeof(Real) + 7) / 8;
+    static constexpr int POST_D = (Q * PR * CWP * (int)sizeof(Real) + 7) / 8;
     static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue staging
     static constexpr int SCR_D = POST_D > WARM_ROWS * CW ? (POST_D > WSUM_ROWS * CW ? POST_D : WSUM_ROWS * CW)
                                                          : (WARM_ROWS * CW > WSUM_ROWS * CW ? WARM_ROWS * CW
                                                                                            : WSUM_ROWS * CW);
     static constexpr int DOUBLES = BAR_D + 2 * NU * PART_D + PART_D + FRING_D + SCR_D;
     static constexpr int XBASE = 2 * BX;                    // first x lane
-    static_assert(NI >= 1 && NI * NT == TY * BX, "block rows must fill the workgroup");
+    static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
+    static_assert((BAR_D + 2 * NU * PART_D + PART_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
     static_assert(2 * TY * NSEG <= NT - XBASE && TY * (BX / K) <= NT - XBASE, "x lanes must fit");
     static_assert(NRING * Q <= NT, "ring-cell loads: one value per thread");
 };
 
-template <typename Real, int FORCE, int TY>
+// Interior cells are handled in pairs (x, x+1), x even, one pair per lane, so
+// that a lane moves both cells' populations with one 16-byte (FP64) or 8-byte
+// (FP32) access.  VEC selects those paired accesses; it requires an even N_x
+// (a pair never straddles the periodic seam).  Odd N_x uses per-cell accesses.
+template <typename Real, int FORCE, int TY, bool VEC>
 __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     constexpr int R = Radius<Real>::value;
     using M = MarchShape<Real, FORCE, TY, R>;
-    constexpr int CW = M::CW, PR = M::PR, RW = M::RW, NB = M::NB, WIN = M::WIN, SEG = M::SEG;
+    using V2 = Real __attribute__((ext_vector_type(2)));
+    constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, WIN = M::WIN, SEG = M::SEG;
     constexpr bool HYB = FORCE == FORCE_HYBRID;
-    __shared__ double sm[M::DOUBLES];
+    __shared__ __align__(16) double sm[M::DOUBLES];
     double* bar = sm;                          // [TY][RW] phi of the block rows, x0-1-R .. x0+64+R
     double* Lx = bar + M::BAR_D;               // [TY][64] forward x sums (or the explicit d/dx)
     double* Qx = Lx + M::PART_D;               // [TY][64] backward x sums
@@ -87,7 +95,7 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     double* Fy = Qxu + (HYB ? M::PART_D : 0);  // [TY][64] y force of the interior
     Real* fring = reinterpret_cast<Real*>(Fy + M::PART_D);                  // [2TY][Q] ring-cell f
     double* scr = Fy + M::PART_D + M::FRING_D;                              // prologue staging
-    Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CW]
+    Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CWP]
 
     const int tid = threadIdx.x, lane = tid & (BX - 1), wave = tid >> 6;
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
@@ -112,8 +120,8 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     const int ccol = wave == 0 ? lane + 1 : (lane < TY ? 0 : CW - 1);   // collision column
     const long xcol = wrap(x0 - 1 + ccol, nx);
     const int rrow = lane % TY;                                           // ring lane's row
-    // Interior cell of this thread (collision and streaming): row tid / 64, column lane.
-    const long xin = wrap(x0 + lane, nx);
+    // Interior pairs of this thread (collision and streaming): pair t = tid + i NT
+    // is row t / 32, cells x0 + 2 (t % 32) and the one after.
 
     // ---------------------------------------------------------------- state
     double win[WIN];                  // phi of rows yb-4 .. yb+TY+3, this lane's column
@@ -123,15 +131,16 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     double pnear[TY], pfar[TY];       // loads of the next block's column rows
     StageRegs<TY * RW> sbar;          // loads of the next block's x bar
     double fr = 0.0;                  // one ring-cell population (tid < 2 TY Q)
-    Real fc[M::NI][Q];                // interior populations (loaded one phase 4 ahead)
+    Real fc[M::NP][2][Q];             // interior populations (loaded one phase 4 ahead)
 
     auto issue = [&](int yn) {        // potential and ring-cell loads of block yn
         stage_issue(sbar, [&](int i) {
             const int r = i / RW, c = i - r * RW;
             return a.phi_in[(long)wrapy(yn + r) * pitch + wrap(x0 - 1 - R + c, nx)];
         });
-        if (tid < M::NRING * Q) {
-            const int e = tid / Q, q = tid - e * Q;
+        {
+            const int i = min(tid, M::NRING * Q - 1);  // past the end: a duplicate, not stored
+            const int e = i / Q, q = i - e * Q;
             const int xr = wrap(e < TY ? x0 - 1 : x0 + BX, nx);
             fr = (double)a.f_in[fidx(xr, wrapy(yn + e % TY), q, nxb)];
         }
@@ -141,19 +150,33 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     // are read again a few blocks later.
     auto issue_f = [&](int yn) {      // interior populations of block yn (after their last use)
 #pragma unroll
-        for (int i = 0; i < M::NI; ++i) {
-            const int yw = wrapy(yn + (tid >> 6) + i * (NT / BX));
+        for (int i = 0; i < M::NP; ++i) {
+            const int t = min(tid + i * NT, M::NPAIR - 1);  // past the end: a duplicate, never used
+            const int yw = wrapy(yn + (t >> 5));
+            const int xa = wrap(x0 + 2 * (t & 31), nx);
+            if (VEC) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) fc[i][q] = __builtin_nontemporal_load(a.f_in + fidx((int)xin, yw, q, nxb));
+                for (int q = 0; q < Q; ++q) {
+                    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(a.f_in + fidx(xa, yw, q, nxb)));
+                    fc[i][0][q] = v.x;
+                    fc[i][1][q] = v.y;
+                }
+            } else {
+                const int xb = wrap(x0 + 2 * (t & 31) + 1, nx);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    fc[i][0][q] = __builtin_nontemporal_load(a.f_in + fidx(xa, yw, q, nxb));
+                    fc[i][1][q] = __builtin_nontemporal_load(a.f_in + fidx(xb, yw, q, nxb));
+                }
+            }
         }
     };
     auto issue_col = [&](int yn) {    // new window rows yn+4 .. and far rows of block yn
-        if (colw) {
+        // (every lane loads; lanes of wavefronts 2-3 load a ring column they do not use)
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                pnear[j] = a.phi_in[(long)wrapy(yn + 4 + j) * pitch + xcol];
-                pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
-            }
+        for (int j = 0; j < TY; ++j) {
+            pnear[j] = a.phi_in[(long)wrapy(yn + 4 + j) * pitch + xcol];
+            pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
         }
     };
     // New block sum from the operands of rows uprev, p[0 .. TY-1]:
@@ -290,13 +313,14 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
     __syncthreads();
 
     // ------------------------------------------------------------ the march
+    // Every global load of the loop is issued unconditionally and in the same
+    // order on every path (the last block loads rows it never uses), so the
+    // compiler's wait counts are exact: each wait covers only the loads it
+    // needs, not the younger prefetches.
     for (int k = 0; k < nblk; ++k) {
         const int yb = yb0 + k * TY;
-        const bool more = k + 1 < nblk;
-        if (more) {
-            issue_col(yb + TY);
-            issue(yb + TY);
-        }
+        issue_col(yb + TY);
+        issue(yb + TY);
 
         // Phase 2: forces; the ring cells are also collided here.
         if (wave == 0) {
@@ -338,7 +362,7 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
                 collide(g9, rho, jx, jy, Fxr, Fyr, a.omega);
                 const int ps = pslot(yb + rrow);
 #pragma unroll
-                for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CW + ccol] = (Real)g9[q];
+                for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CWP + ccol + 1] = (Real)g9[q];
             }
         } else if (a.rec_x) {
             // forward (even lane) and backward (odd lane) x recursion of one
@@ -395,63 +419,99 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
         }
         __syncthreads();
 
-        // Phase 3: collision of the interior cells.
+        // Phase 3: collision of the interior cells, two per lane.
 #pragma unroll
-        for (int i = 0; i < M::NI; ++i) {
-            const int c = tid + i * NT;
-            const int r = c >> 6, cc = lane + 1;
-            const double* br = bar + r * RW + cc + R;
-            double gx, gxu = 0.0;
-            if (a.rec_x) {
-                gx = rd1 * (op(br[1]) - op(br[-1])) + rd2 * (op(br[2]) - op(br[-2])) +
-                     rK * (rr3 * (op(br[3]) - op(br[-3])) + Qx[c] + Lx[c]);
-                if (HYB)
-                    gxu = rd1 * (opu(br[1]) - opu(br[-1])) + rd2 * (opu(br[2]) - opu(br[-2])) +
-                          rK * (rr3 * (opu(br[3]) - opu(br[-3])) + Qxu[c] + Lxu[c]);
-            } else {
-                gx = Lx[c];
-                if (HYB) gxu = Lxu[c];
+        for (int i = 0; i < M::NP; ++i) {
+            const int t = tid + i * NT;
+            if (t < M::NPAIR) {
+                const int r = t >> 5, lx0 = 2 * (t & 31);
+                const int ps = pslot(yb + r);
+                double g[2][Q];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int lx = lx0 + h, c = r * BX + lx;
+                    const double* br = bar + r * RW + lx + 1 + R;
+                    double gx, gxu = 0.0;
+                    if (a.rec_x) {
+                        gx = rd1 * (op(br[1]) - op(br[-1])) + rd2 * (op(br[2]) - op(br[-2])) +
+                             rK * (rr3 * (op(br[3]) - op(br[-3])) + Qx[c] + Lx[c]);
+                        if (HYB)
+                            gxu = rd1 * (opu(br[1]) - opu(br[-1])) + rd2 * (opu(br[2]) - opu(br[-2])) +
+                                  rK * (rr3 * (opu(br[3]) - opu(br[-3])) + Qxu[c] + Lxu[c]);
+                    } else {
+                        gx = Lx[c];
+                        if (HYB) gxu = Lxu[c];
+                    }
+                    const double Fxc = force_from<FORCE>(br[0], gx, gxu, a.A);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) g[h][q] = (double)fc[i][h][q];
+                    double rho, jx, jy;
+                    moments(g[h], rho, jx, jy);
+                    collide(g[h], rho, jx, jy, Fxc, Fy[c], a.omega);
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {  // columns lx0+1, lx0+2 at post index lx0+2 (aligned pair)
+                    V2 v;
+                    v.x = (Real)g[0][q];
+                    v.y = (Real)g[1][q];
+                    *reinterpret_cast<V2*>(post + (q * PR + ps) * CWP + lx0 + 2) = v;
+                }
             }
-            const double Fxc = force_from<FORCE>(br[0], gx, gxu, a.A);
-            double g[Q];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) g[q] = (double)fc[i][q];
-            double rho, jx, jy;
-            moments(g, rho, jx, jy);
-            collide(g, rho, jx, jy, Fxc, Fy[c], a.omega);
-            const int ps = pslot(yb + r);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CW + cc] = (Real)g[q];
         }
         __syncthreads();
 
-        // Phase 4: pull streaming of rows yb-1 .. yb+TY-2 and phi_{t+1}; the
-        // populations of the next block are loaded meanwhile.
-        if (more) issue_f(yb + TY);
+        // Phase 4 begins by committing the loads of step 1 (the bar and ring
+        // cells are not read again in this block; the windows are lane state),
+        // then loads the next block's populations and streams.
+        commit();
+        commit_col();
+        __builtin_amdgcn_sched_barrier(0);  // the commit's waits stay ahead of the new loads and stores
+        issue_f(yb + TY);
+
+        // Pull streaming of rows yb-1 .. yb+TY-2 and phi_{t+1}.
 #pragma unroll
-        for (int i = 0; i < M::NI; ++i) {
-            const int c = tid + i * NT;
-            const int r = c >> 6;
-            const int y = yb - 1 + r, x = x0 + lane;
-            if (y >= ys && y < ye && x < nx) {
-                double g[Q];
+        for (int i = 0; i < M::NP; ++i) {
+            const int t = tid + i * NT;
+            const int r = t >> 5, lx0 = 2 * (t & 31);
+            const int y = yb - 1 + r, x = x0 + lx0;
+            if (t < M::NPAIR && y >= ys && y < ye && x < nx) {
+                double g[2][Q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const Real v = post[(q * PR + pslot(y - ey(q))) * CW + lane + 1 - ex(q)];
-                    __builtin_nontemporal_store(v, a.f_out + fidx(x, y, q, nxb));
-                    g[q] = (double)v;
+                    const Real* src = post + (q * PR + pslot(y - ey(q))) * CWP + lx0 + 2 - ex(q);
+                    const Real v0 = src[0], v1 = src[1];
+                    g[0][q] = (double)v0;
+                    g[1][q] = (double)v1;
+                    if (VEC) {
+                        V2 v;
+                        v.x = v0;
+                        v.y = v1;
+                        __builtin_nontemporal_store(v, reinterpret_cast<V2*>(a.f_out + fidx(x, y, q, nxb)));
+                    } else {
+                        __builtin_nontemporal_store(v0, a.f_out + fidx(x, y, q, nxb));
+                        if (x + 1 < nx) __builtin_nontemporal_store(v1, a.f_out + fidx(x + 1, y, q, nxb));
+                    }
                 }
-                double rho, jx, jy;
-                moments(g, rho, jx, jy);
-                __builtin_nontemporal_store(phi_of<FORCE>(potential(a.eos, rho)), a.phi_out + (long)y * pitch + x);
+                double ph[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    double rho, jx, jy;
+                    moments(g[h], rho, jx, jy);
+                    ph[h] = phi_of<FORCE>(potential(a.eos, rho));
+                }
+                double* pd = a.phi_out + (long)y * pitch + x;
+                if (VEC) {
+                    double __attribute__((ext_vector_type(2))) pv;
+                    pv.x = ph[0];
+                    pv.y = ph[1];
+                    __builtin_nontemporal_store(pv, reinterpret_cast<double __attribute__((ext_vector_type(2)))*>(pd));
+                } else {
+                    __builtin_nontemporal_store(ph[0], pd);
+                    if (x + 1 < nx) __builtin_nontemporal_store(ph[1], pd + 1);
+                }
             }
         }
 
-        // Phase 5: the loads of step 1 into LDS and the column windows.
-        if (more) {
-            commit();
-            commit_col();
-        }
         __syncthreads();
     }
 }
@@ -466,13 +526,22 @@ inline bool march_fits(int ny, int ty) {
     return ny > 2 * R + 1 && ny > (nb + 2) * ty + 3;
 }
 
-// Launch over nchunk y chunks of every 64-column strip (nchunk in [1, ny]).
+// Launch over nchunk y chunks of every 64-column strip (nchunk in [1, ny]);
+// paired 16/8-byte population accesses when N_x is even.
+template <typename Real, int FORCE, int TY>
+inline void launch_march_t(const StepArgs<Real>& a, int nchunk, hipStream_t s) {
+    const dim3 grid((unsigned)(a.nxb * nchunk));
+    if (a.nx % 2 == 0)
+        hipLaunchKernelGGL((k_march<Real, FORCE, TY, true>), grid, dim3(NT), 0, s, a, nchunk);
+    else
+        hipLaunchKernelGGL((k_march<Real, FORCE, TY, false>), grid, dim3(NT), 0, s, a, nchunk);
+}
+
 template <typename Real, int FORCE>
 inline bool launch_march(const StepArgs<Real>& a, int ty, int nchunk, hipStream_t s) {
-    const dim3 grid((unsigned)(a.nxb * nchunk));
     switch (ty) {
-        case 4: hipLaunchKernelGGL((k_march<Real, FORCE, 4>), grid, dim3(NT), 0, s, a, nchunk); return true;
-        case 8: hipLaunchKernelGGL((k_march<Real, FORCE, 8>), grid, dim3(NT), 0, s, a, nchunk); return true;
+        case 4: launch_march_t<Real, FORCE, 4>(a, nchunk, s); return true;
+        case 8: launch_march_t<Real, FORCE, 8>(a, nchunk, s); return true;
         default: return false;
     }
 }
