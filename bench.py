@@ -223,26 +223,36 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
     p.T = 0.7 * tc
     rv, rl, _ = L.maxwell(p, p.T)
     rho0 = torch.from_numpy(I.droplet(256, 256, rv, rl, 48.0, 4.0)).cuda()
-    # per-step costs
+    # per-step costs: forward step; reverse step inside a recorded segment of
+    # `every` steps (how the rollout runs it) and as a single call
     d = L.Domain(p, rho0)
-    st = d.new_states(1)
-    d.save_state(st[0])
     lam = torch.randn((9, 256, 256), dtype=torch.float64, device="cuda")
     lam2 = torch.empty_like(lam)
     grad = torch.zeros(2, dtype=torch.float64, device="cuda")
     ws = d.adjoint_workspace()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    seg = d.new_states(every + 1)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     d.step(10)
+    d.record(seg, every)
+    d.adjoint_steps(seg, every, lam, lam2, grad, ws)
     torch.cuda.synchronize()
     ev[0].record()
     d.step(200)
     ev[1].record()
-    for _ in range(200):
-        d.adjoint_step(st[0], lam, lam2, grad, ws)
+    for _ in range(3):
+        d.adjoint_steps(seg, every, lam, lam2, grad, ws)
     ev[2].record()
+    for _ in range(200):
+        d.adjoint_step(seg[0], lam, lam2, grad, ws)
+    ev[3].record()
+    d.record(seg, every)
+    ev[4].record()
     torch.cuda.synchronize()
     t_fwd = ev[0].elapsed_time(ev[1]) / 200
-    t_adj = ev[1].elapsed_time(ev[2]) / 200
+    t_adj = ev[1].elapsed_time(ev[2]) / (3 * every)
+    t_adj1 = ev[2].elapsed_time(ev[3]) / 200
+    t_rec = ev[3].elapsed_time(ev[4]) / every
+    del seg
     # whole gradient with checkpointing
     pt = L.Params(**{**p.__dict__, "g": 1.02})
     with torch.no_grad():
@@ -269,6 +279,7 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
         "workload": "256x256 CS T=0.7Tc SC+HDM droplet R=48, J = |rho_n - rho(g=1.02)|^2",
         "steps": steps, "checkpoint_every": every, "ms_forward_step": round(t_fwd, 5),
         "ms_adjoint_step": round(t_adj, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
+        "ms_adjoint_step_single_call": round(t_adj1, 5), "ms_record_step": round(t_rec, 5),
         "ms_forward_rollout": round(t_roll, 2), "ms_backward": round(t_back, 2),
         "gradient_over_forward": round((t_roll + t_back) / t_roll, 3), "peak_mib": round(peak / 2 ** 20, 1),
         "J": float(J.item()), "dJ_dg": float(g.grad.item()), "dJ_dT": float(T.grad.item()),

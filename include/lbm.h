@@ -143,7 +143,9 @@ int64_t lbm_step_count(const lbm_domain* d);
  *   0  fused single pass, chosen automatically (the default): the strip-
  *      marching kernel when the HDM gradient takes its geometric form along y
  *      (grad = HDM and ny > 2R + 1, R = 39 for FP64 and 28 for FP32
- *      populations), otherwise independent tiles;
+ *      populations) and its automatic chunks keep >= 16 rows each (large
+ *      lattices), otherwise independent tiles of a height that gives at least
+ *      one tile per compute unit;
  *   1  two-pass reference pair (force + collision + push streaming, then the
  *      potential field), tile_y <= 8 or 16 rows;
  *   2  fused single pass over independent 64 x tile_y tiles, tile_y in
@@ -164,14 +166,24 @@ lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream);
 
 /* ---- state snapshots (checkpoint / restart) ------------------------------ */
 
-/* Bytes of one snapshot of the domain's populations (device, library layout). */
+/* Bytes of one snapshot of the domain: its populations followed by the
+ * potential field of that state (Eq. 8 / Eq. 21), device, library layout. */
 lbm_status lbm_state_bytes(const lbm_domain* d, size_t* bytes);
 
-/* Copy the current populations into `state` (device, lbm_state_bytes) /
- * make `state` the current populations and rebuild its potential field
- * (asynchronous).  The step counter is not changed. */
+/* Copy the current state into `state` (device, lbm_state_bytes, 256-byte
+ * aligned) / make `state` the current state (asynchronous).  The step counter
+ * is not changed. */
 lbm_status lbm_save_state(lbm_domain* d, void* state, hipStream_t stream);
 lbm_status lbm_load_state(lbm_domain* d, const void* state, hipStream_t stream);
+
+/* Record a trajectory (asynchronous): slot 0 of `states` receives the current
+ * state, and slot t+1 the state after step t+1 (the step of Sec. 2, Eq. 1),
+ * for t < nsteps; slot t starts at byte t * stride (stride >= lbm_state_bytes,
+ * a multiple of 256; states 256-byte aligned, nsteps + 1 slots, caller-owned).
+ * The steps are computed from slot to slot without copies; afterwards the
+ * domain holds the last state and its step counter has advanced by nsteps.
+ * This is the recomputation of a checkpointed segment of a reverse sweep. */
+lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride, hipStream_t stream);
 
 /* ---- reverse mode ---------------------------------------------------------- */
 
@@ -186,10 +198,22 @@ lbm_status lbm_adjoint_workspace_bytes(const lbm_domain* d, size_t* bytes);
  *   grad[0] += dJ/dg,  grad[1] += dJ/dT   (J the objective whose dJ/df_{t+1} is lam_next).
  * lam_next, lam_t: device FP64 [9][ny][nx] (distinct buffers); grad: device,
  * 2 doubles; adj_ws: device scratch of lbm_adjoint_workspace_bytes, 256-byte
- * aligned.  The domain's own state is not touched.  LBM_EUNSUPPORTED for FP32
+ * aligned.  The domain's own state is not touched.  state_t carries the
+ * potential field of its populations (lbm_save_state, lbm_record).  LBM_EUNSUPPORTED for FP32
  * domains and for the hybrid force. */
 lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, double* grad,
                             void* adj_ws, size_t adj_ws_bytes, hipStream_t stream);
+
+/* nsteps reverse-mode steps over a recorded trajectory (asynchronous): with
+ * states as written by lbm_record (slot t = the state before step t+1) and
+ * lam = dJ/df_nsteps on entry, lam = dJ/df_0 on return, i.e. lbm_adjoint_step
+ * applied at slots nsteps-1 .. 0 in turn; grad[0] += dJ/dg, grad[1] += dJ/dT
+ * over all the steps (per-workgroup partials are summed step after step and
+ * reduced once, in a fixed order).  lam_tmp: device FP64 [9][ny][nx] scratch,
+ * distinct from lam; adj_ws as for lbm_adjoint_step.  Errors as for
+ * lbm_adjoint_step. */
+lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, int64_t nsteps, double* lam,
+                             double* lam_tmp, double* grad, void* adj_ws, size_t adj_ws_bytes, hipStream_t stream);
 
 /* dJ/drho0 from dJ/df_0 for the initial state f_0 = f^eq(rho0, u0) of Eq. 2 at
  * fixed u0 (asynchronous): drho0 = sum_i lam0_i f^eq_i(1, u0).  lam0 device

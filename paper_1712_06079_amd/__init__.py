@@ -91,13 +91,15 @@ def library():
         L.lbm_adjoint_workspace_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
         L.lbm_adjoint_step.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
         L.lbm_adjoint_rho0.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
+        L.lbm_record.argtypes = [_VP, C.c_int64, _VP, C.c_size_t, _VP]
+        L.lbm_adjoint_steps.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
         L.lbm_destroy.argtypes = [_VP]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
                    "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
-                   "lbm_adjoint_step", "lbm_adjoint_rho0"):
+                   "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -231,10 +233,25 @@ class Domain:
         return nb.value
 
     def new_states(self, n: int):
-        """Device storage for n state snapshots (uint8 tensor [n, state_bytes], rows 256-byte aligned)."""
+        """Device storage for n state snapshots (uint8 tensor [n, stride], stride
+        = state bytes rounded up to 256; the caching allocator aligns the base)."""
         torch = _torch()
-        sb = self.state_bytes()
-        return torch.empty((n, sb), dtype=torch.uint8, device=self._ws.device)
+        sb = (self.state_bytes() + 255) // 256 * 256
+        t = torch.empty((n, sb), dtype=torch.uint8, device=self._ws.device)
+        if t.data_ptr() % 256:
+            raise LBMError(1, "state storage is not 256-byte aligned")
+        return t
+
+    def record(self, states, nsteps: int, stream=None):
+        """states[0] = current state, states[t+1] = state after t+1 steps (t < nsteps)."""
+        if states.shape[0] < nsteps + 1:
+            raise LBMError(1, f"record: {states.shape[0]} slots < nsteps + 1 = {nsteps + 1}")
+        check(library().lbm_record(self._h, int(nsteps), _ptr(states), states.stride(0), _stream(stream)))
+
+    def adjoint_steps(self, states, nsteps: int, lam, lam_tmp, grad, adj_ws, stream=None):
+        """lam <- adjoint of nsteps steps over recorded `states` (slots nsteps-1 .. 0)."""
+        check(library().lbm_adjoint_steps(self._h, _ptr(states), states.stride(0), int(nsteps), _ptr(lam), _ptr(lam_tmp),
+                                          _ptr(grad), _ptr(adj_ws), adj_ws.numel(), _stream(stream)))
 
     def save_state(self, state, stream=None):
         check(library().lbm_save_state(self._h, _ptr(state), _stream(stream)))

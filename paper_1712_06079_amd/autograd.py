@@ -5,8 +5,9 @@ after ``nsteps`` steps from f = f^eq(rho0, 0).  Its backward pass is the
 library's hand-written adjoint step (lbm_adjoint_step) driven in reverse with
 sqrt(N)-style checkpointing: the forward pass keeps one state snapshot every
 ``every`` steps; the backward pass reloads each snapshot, recomputes its
-segment (keeping those ``every`` states) and runs the adjoint steps in reverse
-order.  Memory: (ceil(nsteps / every) + every) snapshots.  Gradients flow to
+segment into ``every + 1`` slots (lbm_record) and runs its adjoint steps in
+reverse order in one call (lbm_adjoint_steps).  Memory: ceil(nsteps / every)
++ every + 1 snapshots.  Gradients flow to
 rho0, to the interaction multiplier g and to the temperature T.
 """
 import dataclasses
@@ -24,12 +25,9 @@ class HDMRollout(torch.autograd.Function):
         d = Domain(p, rho0.detach().contiguous())
         nseg = max(1, math.ceil(nsteps / every))
         ck = d.new_states(nseg)
-        for s in range(nsteps):
-            if s % every == 0:
-                d.save_state(ck[s // every])
-            d.step(1)
-        if nsteps == 0:
-            d.save_state(ck[0])
+        for sidx in range(nseg):
+            d.save_state(ck[sidx])
+            d.step(min(every, nsteps - sidx * every))
         rho = d.moments(want=("rho",))["rho"]
         ctx.d, ctx.ck, ctx.nsteps, ctx.every = d, ck, nsteps, every
         ctx.g_dev, ctx.T_dev = g, T
@@ -44,19 +42,15 @@ class HDMRollout(torch.autograd.Function):
         lam2 = torch.empty_like(lam)
         grad = torch.zeros(2, dtype=torch.float64, device=lam.device)
         ws = d.adjoint_workspace()
-        seg = d.new_states(min(every, max(nsteps, 1)))
+        seg = d.new_states(min(every, max(nsteps, 1)) + 1)
         nseg = max(1, math.ceil(nsteps / every))
         for sidx in reversed(range(nseg)):
             t0, t1 = sidx * every, min(nsteps, sidx * every + every)
             if t1 <= t0:
                 continue
             d.load_state(ck[sidx])
-            for t in range(t0, t1):
-                d.save_state(seg[t - t0])
-                d.step(1)
-            for t in reversed(range(t0, t1)):
-                d.adjoint_step(seg[t - t0], lam, lam2, grad, ws)
-                lam, lam2 = lam2, lam
+            d.record(seg, t1 - t0)
+            d.adjoint_steps(seg, t1 - t0, lam, lam2, grad, ws)
         drho0 = d.adjoint_rho0(lam)
 
         def like(v, ref):

@@ -81,6 +81,7 @@ struct AdjArgs {
     double* __restrict__ ubl;             // U_bar local part
     double* __restrict__ rho;
     double* __restrict__ partial;         // [blocks][2]
+    int accumulate;                       // 1: add this step's partials to the stored ones
     AdjEos e;
 };
 
@@ -104,11 +105,11 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
         double gx = 0, gy = 0;
         for (int j = 1; j <= a.tx; ++j) {
             const double p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
-            gx += a.dx[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
+            gx += a.tab->dx[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
         }
         for (int j = 1; j <= a.ty; ++j) {
             const double p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
-            gy += a.dy[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
+            gy += a.tab->dy[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
         }
         if (x >= a.nx) continue;
         const double Fx = FORCE == FORCE_ZC ? -gx : -2.0 * pc * gx;
@@ -187,8 +188,8 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         const int y = y0 + r;
         if (y >= a.ny) break;
         double dxa = 0, dya = 0;
-        for (int j = 1; j <= a.tx; ++j) dxa += a.dx[j - 1] * (sx.row[r][J + lx + j] - sx.row[r][J + lx - j]);
-        for (int j = 1; j <= a.ty; ++j) dya += a.dy[j - 1] * (sy.col[J + r + j][lx] - sy.col[J + r - j][lx]);
+        for (int j = 1; j <= a.tx; ++j) dxa += a.tab->dx[j - 1] * (sx.row[r][J + lx + j] - sx.row[r][J + lx - j]);
+        for (int j = 1; j <= a.ty; ++j) dya += a.tab->dy[j - 1] * (sy.col[J + r + j][lx] - sy.col[J + r - j][lx]);
         if (x >= a.nx) continue;
         const long op = (long)y * pitch + x;
         double ub;
@@ -221,6 +222,10 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         double t0 = 0, t1 = 0;
         for (int k = 0; k < NT / BX; ++k) { t0 += red[0][k]; t1 += red[1][k]; }
         const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        if (A.accumulate) {  // step after step, in a fixed order per block
+            t0 += A.partial[2 * b];
+            t1 += A.partial[2 * b + 1];
+        }
         A.partial[2 * b] = t0;
         A.partial[2 * b + 1] = t1;
     }

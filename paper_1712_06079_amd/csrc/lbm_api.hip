@@ -66,7 +66,7 @@ int nblocks_x(int nx) { return (nx + lbm::BX - 1) / lbm::BX; }
 
 
 struct Layout {
-    size_t f, phi, part, scr, total;
+    size_t f, phi, part, scr, tab, total;
 };
 
 constexpr int MOM_TY = 16;  // rows per moments tile
@@ -80,7 +80,8 @@ Layout layout_of(const lbm_params* p) {
     const size_t nb = (size_t)nblocks_x(p->nx) * ((p->ny + MOM_TY - 1) / MOM_TY);
     L.part = align256(nb * 4 * sizeof(double));
     L.scr = 256;
-    L.total = 2 * L.f + 2 * L.phi + L.part + L.scr;
+    L.tab = align256(sizeof(lbm::StepTables));
+    L.total = 2 * L.f + 2 * L.phi + L.part + L.scr + L.tab;
     return L;
 }
 
@@ -145,43 +146,73 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
     return LBM_OK;
 }
 
-lbm_status step_once(lbm_domain* d, hipStream_t s) {
-    const int in = d->cur, out = 1 - d->cur;
-    if (d->variant == 1) {
-        dispatch(d, [&](auto real, auto force) {
-            using Real = decltype(real);
-            constexpr int F = decltype(force)::value;
-            auto a = make_args<Real>(d, in, out);
-            if (d->tile_y <= 8) launch_ref<Real, F, 8>(d, a, s);
-            else launch_ref<Real, F, 16>(d, a, s);
-        });
-        HIP_TRY(hipGetLastError());
-        d->cur = out;
-        return launch_phi(d, out, s);
-    }
-    const bool march = d->variant == 3 || (d->variant == 0 && march_eligible(d));
-    if (march && !march_eligible(d))
+// One step from (f_in, phi_in) to (f_out, phi_out), any of the domain's
+// buffers or snapshot slots, with the selected kernel.
+// Automatic choice (variant 0): the marching kernel when its chunks keep at
+// least 16 rows each (shorter chunks spend most of their time in the chunk
+// prologue), otherwise tiles, halved in height until there are at least as
+// many tiles as compute units.
+constexpr int MARCH_MIN_ROWS = 16;
+
+template <typename Real>
+int auto_tile(const lbm_domain* d) {
+    int ty = sizeof(Real) == 8 ? 8 : 16;
+    while (ty > 4 && (long)d->nxb * ((d->p.ny + ty - 1) / ty) < d->ncu) ty /= 2;
+    return ty;
+}
+
+lbm_status run_step(lbm_domain* d, const void* f_in, const double* phi_in, void* f_out, double* phi_out, hipStream_t s) {
+    if (d->variant == 3 && !march_eligible(d))
         return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and a longer y axis (ny = %d)", d->p.ny);
     lbm_status st = LBM_OK;
     dispatch(d, [&](auto real, auto force) {
         using Real = decltype(real);
         constexpr int F = decltype(force)::value;
-        auto a = make_args<Real>(d, in, out);
-        if (march) {
+        bool march = d->variant == 3;
+        if (d->variant == 0 && march_eligible(d)) {
+            int nchunk = 1;
+            st = march_chunks<Real, F>(d, march_rows(d), &nchunk);
+            march = st == LBM_OK && d->p.ny / nchunk >= MARCH_MIN_ROWS;
+        }
+        if (st != LBM_OK) return;
+        auto a = make_args<Real>(d, d->cur, 1 - d->cur);
+        a.f_in = static_cast<const Real*>(f_in);
+        a.phi_in = phi_in;
+        a.f_out = static_cast<Real*>(f_out);
+        a.phi_out = phi_out;
+        if (d->variant == 1) {
+            if (d->tile_y <= 8) launch_ref<Real, F, 8>(d, a, s);
+            else launch_ref<Real, F, 16>(d, a, s);
+            auto b = a;  // potential field of the new state
+            b.f_in = a.f_out;
+            hipLaunchKernelGGL((lbm::k_phi<Real, F>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, s, b);
+        } else if (march) {
             const int ty = march_rows(d);
             int nchunk = 1;
             st = march_chunks<Real, F>(d, ty, &nchunk);
             if (st == LBM_OK && !lbm::launch_march<Real, F>(a, ty, nchunk, s))
                 st = fail(LBM_EUNSUPPORTED, "marching kernel: unsupported block height %d", ty);
-        } else if (!lbm::launch_fused<Real, F>(a, d->variant == 0 ? 0 : d->tile_y, s)) {
+        } else if (!lbm::launch_fused<Real, F>(a, d->variant == 0 ? auto_tile<Real>(d) : d->tile_y, s)) {
             st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", d->tile_y);
         }
     });
     if (st != LBM_OK) return st;
     HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status step_once(lbm_domain* d, hipStream_t s) {
+    const int in = d->cur, out = 1 - d->cur;
+    lbm_status st = run_step(d, d->ws + d->off_f[in], reinterpret_cast<const double*>(d->ws + d->off_phi[in]),
+                             d->ws + d->off_f[out], reinterpret_cast<double*>(d->ws + d->off_phi[out]), s);
+    if (st != LBM_OK) return st;
     d->cur = out;
     return LBM_OK;
 }
+
+// Bytes of the population and potential parts of a snapshot.
+size_t f_bytes(const lbm_domain* d) { return d->off_f[1]; }
+size_t phi_bytes(const lbm_domain* d) { return d->off_phi[1] - d->off_phi[0]; }
 
 }  // namespace
 
@@ -277,6 +308,15 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
         d->ty = lbm_host::hdm_taps(p->ny, radius);
         lbm_host::hdm_row(p->nx, d->tx, d->dx);
         lbm_host::hdm_row(p->ny, d->ty, d->dy);
+    }
+    d->off_tab = d->off_scr + L.scr;
+    build_tables(d);
+    {
+        hipError_t et = hipMemcpyAsync(d->ws + d->off_tab, &d->htab, sizeof(d->htab), hipMemcpyHostToDevice, stream);
+        if (et != hipSuccess) {
+            delete d;
+            return fail(LBM_EDEVICE, "uploading the stencil tables: %s", hipGetErrorString(et));
+        }
     }
 
     // validate rho0 on the device
@@ -402,24 +442,57 @@ lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream) {
 
 lbm_status lbm_state_bytes(const lbm_domain* d, size_t* bytes) {
     if (!d || !bytes) return fail(LBM_EINVAL, "NULL argument");
-    *bytes = d->off_f[1];
+    *bytes = f_bytes(d) + phi_bytes(d);
     return LBM_OK;
 }
 
 lbm_status lbm_save_state(lbm_domain* d, void* state, hipStream_t stream) {
     if (!d || !state) return fail(LBM_EINVAL, "NULL argument");
-    HIP_TRY(hipMemcpyAsync(state, d->ws + d->off_f[d->cur], d->off_f[1], hipMemcpyDeviceToDevice, stream));
+    if (((uintptr_t)state & 255) != 0) return fail(LBM_EINVAL, "state must be 256-byte aligned");
+    char* st = static_cast<char*>(state);
+    HIP_TRY(hipMemcpyAsync(st, d->ws + d->off_f[d->cur], f_bytes(d), hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(st + f_bytes(d), d->ws + d->off_phi[d->cur], phi_bytes(d), hipMemcpyDeviceToDevice, stream));
     return LBM_OK;
 }
 
 lbm_status lbm_load_state(lbm_domain* d, const void* state, hipStream_t stream) {
     if (!d || !state) return fail(LBM_EINVAL, "NULL argument");
-    HIP_TRY(hipMemcpyAsync(d->ws + d->off_f[d->cur], state, d->off_f[1], hipMemcpyDeviceToDevice, stream));
-    return launch_phi(d, d->cur, stream);
+    if (((uintptr_t)state & 255) != 0) return fail(LBM_EINVAL, "state must be 256-byte aligned");
+    const char* st = static_cast<const char*>(state);
+    HIP_TRY(hipMemcpyAsync(d->ws + d->off_f[d->cur], st, f_bytes(d), hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d->ws + d->off_phi[d->cur], st + f_bytes(d), phi_bytes(d), hipMemcpyDeviceToDevice, stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride, hipStream_t stream) {
+    if (!d || !states) return fail(LBM_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+    if (((uintptr_t)states & 255) != 0 || (stride & 255) != 0) return fail(LBM_EINVAL, "states and stride must be 256-byte aligned");
+    if (stride < f_bytes(d) + phi_bytes(d)) return fail(LBM_EINVAL, "stride %zu < state bytes %zu", stride, f_bytes(d) + phi_bytes(d));
+    char* base = static_cast<char*>(states);
+    lbm_status st = lbm_save_state(d, base, stream);
+    if (st != LBM_OK) return st;
+    const size_t fb = f_bytes(d);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        char* in = base + (size_t)t * stride;
+        char* out = in + stride;
+        st = run_step(d, in, reinterpret_cast<const double*>(in + fb), out, reinterpret_cast<double*>(out + fb), stream);
+        if (st != LBM_OK) return st;
+    }
+    if (nsteps > 0) {
+        st = lbm_load_state(d, base + (size_t)nsteps * stride, stream);
+        if (st != LBM_OK) return st;
+        d->steps += nsteps;
+    }
+    return LBM_OK;
 }
 
 namespace {
-constexpr int ADJ_TY = 8;
+// Rows per tile of the reverse kernels: 8, or 4 when 8-row tiles would leave
+// compute units idle (small lattices).  The partials buffer is sized for 4.
+int adj_ty(const lbm_domain* d) {
+    return (long)d->nxb * ((d->p.ny + 7) / 8) >= d->ncu ? 8 : 4;
+}
 struct AdjLayout {
     size_t plane, f, part, total;
 };
@@ -427,9 +500,9 @@ AdjLayout adj_layout(const lbm_domain* d) {
     AdjLayout L;
     L.plane = align256((size_t)d->pitch * d->p.ny * sizeof(double));
     L.f = d->off_f[1];
-    const size_t nb = (size_t)d->nxb * ((d->p.ny + ADJ_TY - 1) / ADJ_TY);
+    const size_t nb = (size_t)d->nxb * ((d->p.ny + 3) / 4);
     L.part = align256(nb * 2 * sizeof(double));
-    L.total = 5 * L.plane + L.part;
+    L.total = 4 * L.plane + L.part;
     return L;
 }
 double alpha_prime(const lbm_domain* d) {
@@ -451,28 +524,25 @@ lbm_status lbm_adjoint_workspace_bytes(const lbm_domain* d, size_t* bytes) {
     return LBM_OK;
 }
 
-lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, double* grad,
-                            void* adj_ws, size_t adj_ws_bytes, hipStream_t stream) {
-    if (!d || !state_t || !lam_next || !lam_t || !grad || !adj_ws) return fail(LBM_EINVAL, "NULL argument");
-    if (lam_next == lam_t) return fail(LBM_EINVAL, "lam_next and lam_t must be distinct buffers");
-    if (d->p.prec != LBM_F64) return fail(LBM_EUNSUPPORTED, "the adjoint step is implemented for FP64 domains");
-    if (d->p.force == LBM_FORCE_HYBRID) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the SC and ZC forces");
-    if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+namespace {
+// Kernels of one reverse step at snapshot `state_t` (populations and their
+// potential field); the per-block partials of dJ/dg, dJ/dT are written
+// (accumulate = 0) or added to (accumulate = 1).
+lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, char* w,
+                           int accumulate, hipStream_t stream) {
     AdjLayout L = adj_layout(d);
-    if (adj_ws_bytes < L.total) return fail(LBM_ENOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);
-    char* w = static_cast<char*>(adj_ws);
     lbm::AdjArgs A;
     std::memset(&A, 0, sizeof(A));
     A.s = make_args<double>(d, d->cur, d->cur);
     A.s.f_in = static_cast<const double*>(state_t);
-    double* phi = reinterpret_cast<double*>(w);
-    A.s.phi_in = phi;
-    A.s.phi_out = phi;
-    A.ax = reinterpret_cast<double*>(w + L.plane);
-    A.ay = reinterpret_cast<double*>(w + 2 * L.plane);
-    A.ubl = reinterpret_cast<double*>(w + 3 * L.plane);
-    A.rho = reinterpret_cast<double*>(w + 4 * L.plane);
-    A.partial = reinterpret_cast<double*>(w + 5 * L.plane);
+    A.s.phi_in = reinterpret_cast<const double*>(static_cast<const char*>(state_t) + f_bytes(d));
+    A.s.phi_out = nullptr;
+    A.ax = reinterpret_cast<double*>(w);
+    A.ay = reinterpret_cast<double*>(w + L.plane);
+    A.ubl = reinterpret_cast<double*>(w + 2 * L.plane);
+    A.rho = reinterpret_cast<double*>(w + 3 * L.plane);
+    A.partial = reinterpret_cast<double*>(w + 4 * L.plane);
+    A.accumulate = accumulate;
     A.lam_next = lam_next;
     A.lam = lam_t;
     A.e.kind = d->p.eos;
@@ -482,27 +552,85 @@ lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* la
     A.e.c_att = d->p.k * d->p.a * d->alpha;
     A.e.c_attT = d->p.k * d->p.a * alpha_prime(d);
     A.e.kR = d->p.k * d->p.R;
-    // potential field of state_t
-    {
-        lbm::StepArgs<double> pa = A.s;
-        pa.phi_out = phi;
-        if (d->p.force == LBM_FORCE_SC)
-            hipLaunchKernelGGL((lbm::k_phi<double, lbm::FORCE_SC>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, stream, pa);
-        else
-            hipLaunchKernelGGL((lbm::k_phi<double, lbm::FORCE_ZC>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, stream, pa);
-        HIP_TRY(hipGetLastError());
-    }
-    dim3 grid(d->nxb, (d->p.ny + ADJ_TY - 1) / ADJ_TY);
+    const int ty = adj_ty(d);
+    dim3 grid(d->nxb, (d->p.ny + ty - 1) / ty);
+    auto launch = [&](auto force, auto tyc) {
+        constexpr int F = decltype(force)::value, TY = decltype(tyc)::value;
+        hipLaunchKernelGGL((lbm::k_adj_local<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
+        hipLaunchKernelGGL((lbm::k_adj_nonlocal<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
+    };
+    using SC = std::integral_constant<int, lbm::FORCE_SC>;
+    using ZC = std::integral_constant<int, lbm::FORCE_ZC>;
+    using T4 = std::integral_constant<int, 4>;
+    using T8 = std::integral_constant<int, 8>;
     if (d->p.force == LBM_FORCE_SC) {
-        hipLaunchKernelGGL((lbm::k_adj_local<lbm::FORCE_SC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
-        hipLaunchKernelGGL((lbm::k_adj_nonlocal<lbm::FORCE_SC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+        if (ty == 8) launch(SC(), T8()); else launch(SC(), T4());
     } else {
-        hipLaunchKernelGGL((lbm::k_adj_local<lbm::FORCE_ZC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
-        hipLaunchKernelGGL((lbm::k_adj_nonlocal<lbm::FORCE_ZC, ADJ_TY>), grid, dim3(lbm::NT), 0, stream, A);
+        if (ty == 8) launch(ZC(), T8()); else launch(ZC(), T4());
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(lbm::k_adj_accumulate, dim3(1), dim3(lbm::NT), 0, stream, A.partial, (long)grid.x * grid.y, grad);
+    return LBM_OK;
+}
+
+lbm_status adjoint_check(lbm_domain* d, const void* adj_ws, size_t adj_ws_bytes) {
+    if (d->p.prec != LBM_F64) return fail(LBM_EUNSUPPORTED, "the adjoint step is implemented for FP64 domains");
+    if (d->p.force == LBM_FORCE_HYBRID) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the SC and ZC forces");
+    if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+    AdjLayout L = adj_layout(d);
+    if (adj_ws_bytes < L.total) return fail(LBM_ENOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);
+    return LBM_OK;
+}
+
+lbm_status adjoint_reduce(lbm_domain* d, char* w, double* grad, hipStream_t stream) {
+    AdjLayout L = adj_layout(d);
+    const int ty = adj_ty(d);
+    const long nb = (long)d->nxb * ((d->p.ny + ty - 1) / ty);
+    hipLaunchKernelGGL(lbm::k_adj_accumulate, dim3(1), dim3(lbm::NT), 0, stream,
+                       reinterpret_cast<const double*>(w + 4 * L.plane), nb, grad);
     HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t, double* grad,
+                            void* adj_ws, size_t adj_ws_bytes, hipStream_t stream) {
+    if (!d || !state_t || !lam_next || !lam_t || !grad || !adj_ws) return fail(LBM_EINVAL, "NULL argument");
+    if (lam_next == lam_t) return fail(LBM_EINVAL, "lam_next and lam_t must be distinct buffers");
+    lbm_status st = adjoint_check(d, adj_ws, adj_ws_bytes);
+    if (st != LBM_OK) return st;
+    char* w = static_cast<char*>(adj_ws);
+    st = adjoint_kernels(d, state_t, lam_next, lam_t, w, 0, stream);
+    if (st != LBM_OK) return st;
+    return adjoint_reduce(d, w, grad, stream);
+}
+
+lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, int64_t nsteps, double* lam,
+                             double* lam_tmp, double* grad, void* adj_ws, size_t adj_ws_bytes, hipStream_t stream) {
+    if (!d || !states || !lam || !lam_tmp || !grad || !adj_ws) return fail(LBM_EINVAL, "NULL argument");
+    if (lam == lam_tmp) return fail(LBM_EINVAL, "lam and lam_tmp must be distinct buffers");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+    if (((uintptr_t)states & 255) != 0 || (stride & 255) != 0) return fail(LBM_EINVAL, "states and stride must be 256-byte aligned");
+    if (stride < f_bytes(d) + phi_bytes(d)) return fail(LBM_EINVAL, "stride %zu < state bytes %zu", stride, f_bytes(d) + phi_bytes(d));
+    lbm_status st = adjoint_check(d, adj_ws, adj_ws_bytes);
+    if (st != LBM_OK) return st;
+    if (nsteps == 0) return LBM_OK;
+    char* w = static_cast<char*>(adj_ws);
+    const char* base = static_cast<const char*>(states);
+    double* cur = lam;
+    double* nxt = lam_tmp;
+    for (int64_t t = nsteps - 1; t >= 0; --t) {
+        st = adjoint_kernels(d, base + (size_t)t * stride, cur, nxt, w, t == nsteps - 1 ? 0 : 1, stream);
+        if (st != LBM_OK) return st;
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    st = adjoint_reduce(d, w, grad, stream);
+    if (st != LBM_OK) return st;
+    if (cur != lam) {
+        const size_t lb = (size_t)lbm::Q * d->p.nx * d->p.ny * sizeof(double);
+        HIP_TRY(hipMemcpyAsync(lam, cur, lb, hipMemcpyDeviceToDevice, stream));
+    }
     return LBM_OK;
 }
 

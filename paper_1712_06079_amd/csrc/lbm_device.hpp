@@ -126,8 +126,19 @@ __device__ inline int wrap(int v, int n) {
     return v;
 }
 
-// Kernel arguments of one domain step (passed by value; the coefficient
-// tables travel in the kernel-argument segment and are read as scalars).
+// Coefficient tables of a domain's Eq. 20 stencil, in device memory (a small
+// region of the domain workspace); kernels read them with uniform (scalar)
+// loads.  Keeping them out of the kernel arguments keeps launches cheap.
+struct StepTables {
+    double dx[JCAP];  // d_1 .. d_tx along x
+    double dy[JCAP];  // d_1 .. d_ty along y
+    // Sign-folded tables for the blocked stencil: tab[i] = c(i - TAB_OFF),
+    // c(n) = sign(n) d_|n| for 1 <= |n| <= taps, else 0.
+    double tx_tab[TAB];
+    double ty_tab[TAB];
+};
+
+// Kernel arguments of one domain step (passed by value).
 template <typename Real>
 struct StepArgs {
     const Real* __restrict__ f_in;
@@ -139,12 +150,7 @@ struct StepArgs {
     double omega;     // 1 / tau
     double A;         // hybrid weight (Eq. 9)
     DevEos eos;
-    double dx[JCAP];  // d_1 .. d_tx along x
-    double dy[JCAP];  // d_1 .. d_ty along y
-    // Sign-folded tables for the blocked stencil: tab[i] = c(i - TAB_OFF),
-    // c(n) = sign(n) d_|n| for 1 <= |n| <= taps, else 0.
-    double tx_tab[TAB];
-    double ty_tab[TAB];
+    const StepTables* __restrict__ tab;  // the domain's coefficient tables (device)
     // Geometric form of the infinite-line row (d_j = C r^j for j >= 3), used
     // along an axis whose length exceeds 2R + 1 (there the periodic row equals
     // it to rounding): rec_x / rec_y select it per axis; rK = C / (1 - r).

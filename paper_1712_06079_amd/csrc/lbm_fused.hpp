@@ -128,8 +128,10 @@ __device__ inline double force_from(double phic, double g, double gu, double A) 
 // One TX x TY tile with origin (x0, y0) of the domain described by `a`;
 // `sm` is the workgroup's LDS of FusedShape::DOUBLES doubles.  RX and RY are the
 // stencil radii staged along x and y (>= the domain's taps along each axis).
+// `tabs` is LDS for the two sign-folded coefficient tables (2 TAB doubles),
+// staged here from the domain's device tables.
 template <typename Real, int FORCE, int TX, int TY, int K, int RX, int RY>
-__device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, double* sm) {
+__device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, double* sm, double* tabs) {
     using S = FusedShape<Real, TX, TY, K, RX, RY>;
     constexpr int CW = S::CW, CH = S::CH;
     double* rowr = sm;                          // [CH][RW]   phi rows  x0-1-RX .. x0+TX+RX (+ segment padding)
@@ -174,9 +176,13 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
 
     __builtin_amdgcn_sched_barrier(0);
 
-    // Phase 1: the cross into LDS.
+    // Phase 1: the cross and the coefficient tables into LDS.
     stage_commit(rowr, srow);
     stage_commit(colr, scol);
+    for (int i = tid; i < TAB; i += NT) {
+        tabs[i] = a.tab->tx_tab[i];
+        tabs[TAB + i] = a.tab->ty_tab[i];
+    }
     __syncthreads();
 
     // Phase 2: gradients and force.  Axes longer than 2R + 1 use the geometric
@@ -215,7 +221,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
         double acc[K], accu[K];
         if (it < nix) {
             const int cy = it % CH, s = it / CH;  // consecutive lanes: consecutive rows
-            stencil_window<FORCE, K, RX>(rowr + cy * S::RW + s * K, 1, a.tx_tab, acc, accu);
+            stencil_window<FORCE, K, RX>(rowr + cy * S::RW + s * K, 1, tabs, acc, accu);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int cx = s * K + k;
@@ -224,7 +230,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
         } else {
             const int yt = it - nix;
             const int cx = yt % CW, s = yt / CW;  // consecutive lanes: consecutive columns
-            stencil_window<FORCE, K, RY>(colr + (s * K) * CW + cx, CW, a.ty_tab, acc, accu);
+            stencil_window<FORCE, K, RY>(colr + (s * K) * CW + cx, CW, tabs + TAB, acc, accu);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int cy = s * K + k;
@@ -290,9 +296,10 @@ template <typename Real, int FORCE, int TX, int TY, int K>
 __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
     constexpr int R = Radius<Real>::value;
     __shared__ double sm[FusedShape<Real, TX, TY, K, R, R>::DOUBLES];
+    __shared__ double tabs[2 * TAB];
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int ty = t / gridDim.x, tx = t - ty * gridDim.x;
-    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, tx * TX, ty * TY, sm);
+    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, tx * TX, ty * TY, sm, tabs);
 }
 
 // Batched step: one launch advances every domain of a batch by one step.
@@ -310,9 +317,10 @@ __global__ void __launch_bounds__(NT) k_batch(const StepArgs<Real>* __restrict__
                                               const BatchTile* __restrict__ tiles, int ntiles) {
     constexpr int RX = Radius<Real>::value;
     __shared__ double sm[FusedShape<Real, BX, TY, 4, RX, RY>::DOUBLES];
+    __shared__ double tabs[2 * TAB];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const BatchTile w = tiles[t];
-        fused_tile<Real, FORCE, BX, TY, 4, RX, RY>(descs[w.d], w.x0, w.y0, sm);
+        fused_tile<Real, FORCE, BX, TY, 4, RX, RY>(descs[w.d], w.x0, w.y0, sm, tabs);
         __syncthreads();
     }
 }

@@ -27,7 +27,8 @@ struct lbm_domain {
     int march_occ[2];  // resident marching workgroups per CU (block rows 4, 8; 0 = not queried)
     char* ws;
     size_t ws_bytes;
-    size_t off_f[2], off_phi[2], off_part, off_scr;
+    size_t off_f[2], off_phi[2], off_part, off_scr, off_tab;
+    lbm::StepTables htab;  // host copy of the device tables (source of their upload)
     int tx, ty;
     double dx[lbm::JCAP], dy[lbm::JCAP];
 };
@@ -74,10 +75,7 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     a.eos.c_att = g * k * d->p.a * d->alpha;
     a.eos.c_lin = g / 3.0;
     a.eos.b = d->p.b;
-    for (int j = 0; j < lbm::JCAP; ++j) {
-        a.dx[j] = d->dx[j];
-        a.dy[j] = d->dy[j];
-    }
+    a.tab = reinterpret_cast<const lbm::StepTables*>(d->ws + d->off_tab);
     // geometric recursion along axes longer than 2R + 1 (HDM only)
     const int R = lbm::Radius<Real>::value;
     a.rec_x = (d->p.grad == LBM_GRAD_HDM && d->p.nx > 2 * R + 1) ? 1 : 0;
@@ -87,13 +85,21 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     a.rr3 = a.rr * a.rr * a.rr;
     a.rr4 = a.rr3 * a.rr;
     a.rK = C / (1.0 - a.rr);
-    // sign-folded tables of the blocked stencil: tab[i] = c(i - TAB_OFF)
+    return a;
+}
+
+// Fill d->htab from the one-sided rows d->dx, d->dy (taps d->tx, d->ty).
+inline void build_tables(lbm_domain* d) {
+    std::memset(&d->htab, 0, sizeof(d->htab));
+    for (int j = 0; j < lbm::JCAP; ++j) {
+        d->htab.dx[j] = d->dx[j];
+        d->htab.dy[j] = d->dy[j];
+    }
     for (int i = 0; i < lbm::TAB; ++i) {
         const int n = i - lbm::TAB_OFF, an = n < 0 ? -n : n;
-        a.tx_tab[i] = (an >= 1 && an <= d->tx) ? (n > 0 ? d->dx[an - 1] : -d->dx[an - 1]) : 0.0;
-        a.ty_tab[i] = (an >= 1 && an <= d->ty) ? (n > 0 ? d->dy[an - 1] : -d->dy[an - 1]) : 0.0;
+        d->htab.tx_tab[i] = (an >= 1 && an <= d->tx) ? (n > 0 ? d->dx[an - 1] : -d->dx[an - 1]) : 0.0;
+        d->htab.ty_tab[i] = (an >= 1 && an <= d->ty) ? (n > 0 ? d->dy[an - 1] : -d->dy[an - 1]) : 0.0;
     }
-    return a;
 }
 
 // Call fn(Real{}, integral_constant<FORCE>) for the compile-time types of d.

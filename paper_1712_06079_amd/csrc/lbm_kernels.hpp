@@ -159,21 +159,21 @@ __device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& 
     const double pc = s.row[r][J + lx];
     if (FORCE == FORCE_ZC) {
         double gx = 0, gy = 0;
-        for (int j = 1; j <= a.tx; ++j) gx += a.dx[j - 1] * (s.row[r][J + lx + j] - s.row[r][J + lx - j]);
-        for (int j = 1; j <= a.ty; ++j) gy += a.dy[j - 1] * (s.col[J + r + j][lx] - s.col[J + r - j][lx]);
+        for (int j = 1; j <= a.tx; ++j) gx += a.tab->dx[j - 1] * (s.row[r][J + lx + j] - s.row[r][J + lx - j]);
+        for (int j = 1; j <= a.ty; ++j) gy += a.tab->dy[j - 1] * (s.col[J + r + j][lx] - s.col[J + r - j][lx]);
         Fx = -gx;
         Fy = -gy;
     } else {
         double gx = 0, gy = 0, ux = 0, uy = 0;
         for (int j = 1; j <= a.tx; ++j) {
             const double p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
-            gx += a.dx[j - 1] * (fabs(p) - fabs(m));
-            if (FORCE == FORCE_HYBRID) ux += a.dx[j - 1] * (p * fabs(p) - m * fabs(m));
+            gx += a.tab->dx[j - 1] * (fabs(p) - fabs(m));
+            if (FORCE == FORCE_HYBRID) ux += a.tab->dx[j - 1] * (p * fabs(p) - m * fabs(m));
         }
         for (int j = 1; j <= a.ty; ++j) {
             const double p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
-            gy += a.dy[j - 1] * (fabs(p) - fabs(m));
-            if (FORCE == FORCE_HYBRID) uy += a.dy[j - 1] * (p * fabs(p) - m * fabs(m));
+            gy += a.tab->dy[j - 1] * (fabs(p) - fabs(m));
+            if (FORCE == FORCE_HYBRID) uy += a.tab->dy[j - 1] * (p * fabs(p) - m * fabs(m));
         }
         Fx = -2.0 * pc * gx;
         Fy = -2.0 * pc * gy;

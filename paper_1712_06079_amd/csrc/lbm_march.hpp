@@ -79,14 +79,17 @@ struct MarchShape {
 // that a lane moves both cells' populations with one 16-byte (FP64) or 8-byte
 // (FP32) access.  VEC selects those paired accesses; it requires an even N_x
 // (a pair never straddles the periodic seam).  Odd N_x uses per-cell accesses.
+// At least two waves per SIMD (two workgroups per CU): the register budget
+// (VGPRs + AGPRs <= 256) is a hard limit, not a hint.
 template <typename Real, int FORCE, int TY, bool VEC>
-__global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_march(StepArgs<Real> a, int nchunk) {
     constexpr int R = Radius<Real>::value;
     using M = MarchShape<Real, FORCE, TY, R>;
     using V2 = Real __attribute__((ext_vector_type(2)));
     constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, WIN = M::WIN, SEG = M::SEG;
     constexpr bool HYB = FORCE == FORCE_HYBRID;
     __shared__ __align__(16) double sm[M::DOUBLES];
+    __shared__ double ctab[TAB];               // sign-folded x coefficients (staged in the prologue)
     double* bar = sm;                          // [TY][RW] phi of the block rows, x0-1-R .. x0+64+R
     double* Lx = bar + M::BAR_D;               // [TY][64] forward x sums (or the explicit d/dx)
     double* Qx = Lx + M::PART_D;               // [TY][64] backward x sums
@@ -281,6 +284,7 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
         for (int j = 0; j < WIN; ++j) win[j] = a.phi_in[(long)wrapy(yb0 - 4 + j) * pitch + xcol];
     }
     stage_rows(yb0 - R, M::WARM_ROWS);
+    for (int i = tid; i < TAB; i += NT) ctab[i] = a.tab->tx_tab[i];
     __syncthreads();
     if (colw) {
         for (int m = 1; m <= R - 4; ++m) {
@@ -340,15 +344,40 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
                         gyu = gu[o];
                         phic = win[o + 4];
                     }
-                // explicit d/dx of the ring cell over the bar (sign-folded table)
+                // explicit d/dx of the ring cell over the bar: on a long x axis
+                // the row is geometric (d_n = C r^n, n >= 3) and its weights are
+                // generated in registers (four interleaved chains); a short axis
+                // uses the periodic row's table
                 const double* br = bar + rrow * RW + ccol + R;
                 double sx[4] = {0.0, 0.0, 0.0, 0.0}, sxu[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums
+                if (a.rec_x) {
+                    double w[4];
+                    w[0] = rK * (1.0 - rr) * rr3;
+                    w[1] = w[0] * rr;
+                    w[2] = w[1] * rr;
+                    w[3] = w[2] * rr;
+#pragma unroll 4
+                    for (int n = 3; n <= R; ++n) {
+                        const int k = (n - 3) & 3;
+                        const double vp = br[n], vm = br[-n];
+                        sx[k] = fma(w[k], op(vp) - op(vm), sx[k]);
+                        if (HYB) sxu[k] = fma(w[k], opu(vp) - opu(vm), sxu[k]);
+                        w[k] *= rr4;
+                    }
+                    sx[0] = fma(rd1, op(br[1]) - op(br[-1]), sx[0]);
+                    sx[1] = fma(rd2, op(br[2]) - op(br[-2]), sx[1]);
+                    if (HYB) {
+                        sxu[0] = fma(rd1, opu(br[1]) - opu(br[-1]), sxu[0]);
+                        sxu[1] = fma(rd2, opu(br[2]) - opu(br[-2]), sxu[1]);
+                    }
+                } else {
 #pragma unroll 8
-                for (int n = 1; n <= R; ++n) {
-                    const double c = a.tx_tab[TAB_OFF + n];
-                    const double vp = br[n], vm = br[-n];
-                    sx[n & 3] = fma(c, op(vp) - op(vm), sx[n & 3]);
-                    if (HYB) sxu[n & 3] = fma(c, opu(vp) - opu(vm), sxu[n & 3]);
+                    for (int n = 1; n <= R; ++n) {
+                        const double c = ctab[TAB_OFF + n];
+                        const double vp = br[n], vm = br[-n];
+                        sx[n & 3] = fma(c, op(vp) - op(vm), sx[n & 3]);
+                        if (HYB) sxu[n & 3] = fma(c, opu(vp) - opu(vm), sxu[n & 3]);
+                    }
                 }
                 const double gx = (sx[0] + sx[1]) + (sx[2] + sx[3]);
                 const double gxu = (sxu[0] + sxu[1]) + (sxu[2] + sxu[3]);
@@ -409,7 +438,7 @@ __global__ void __launch_bounds__(NT) k_march(StepArgs<Real> a, int nchunk) {
             if (xi < TY * (BX / M::K)) {
                 const int r = xi % TY, sg = xi / TY;
                 double acc[M::K], accu[M::K];
-                stencil_window<FORCE, M::K, R>(bar + r * RW + 1 + sg * M::K, 1, a.tx_tab, acc, accu);
+                stencil_window<FORCE, M::K, R>(bar + r * RW + 1 + sg * M::K, 1, ctab, acc, accu);
 #pragma unroll
                 for (int j = 0; j < M::K; ++j) {
                     Lx[r * BX + sg * M::K + j] = acc[j];

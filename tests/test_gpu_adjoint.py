@@ -124,3 +124,62 @@ def test_adjoint_unsupported_variants():
     with pytest.raises(L.LBMError) as e:
         d.adjoint_step(st[0], lam, lam.clone(), torch.zeros(2, dtype=torch.float64, device="cuda"), d.adjoint_workspace())
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("variant,nx,ny", [(0, 64, 96), (2, 70, 37), (1, 40, 30), (3, 66, 90)])
+def test_record_equals_stepping(variant, nx, ny):
+    """lbm_record's slots are bitwise the states that stepping and saving give."""
+    po, rho0, _, _ = case("cs", "sc", nx, ny)
+    n = 7
+    a = L.Domain(lib_params(po), dev(rho0))
+    b = L.Domain(lib_params(po), dev(rho0))
+    a.set_kernel(variant, 0)
+    b.set_kernel(variant, 0)
+    rec = a.new_states(n + 1)
+    a.record(rec, n)
+    ref = b.new_states(n + 1)
+    for t in range(n + 1):
+        b.save_state(ref[t])
+        if t < n:
+            b.step(1)
+    torch.cuda.synchronize()
+    # compare the lattice cells (columns x >= nx of the 64-aligned rows are
+    # padding that no kernel reads or writes)
+    pitch = (nx + 63) // 64 * 64
+    phib = (pitch * ny * 8 + 255) // 256 * 256
+    fb = a.state_bytes() - phib
+    c = L.Domain(lib_params(po), dev(rho0))
+    for t in range(n + 1):
+        c.load_state(rec[t])
+        fr = c.populations()
+        c.load_state(ref[t])
+        assert torch.equal(fr, c.populations()), t
+        pr = rec[t, fb:fb + pitch * ny * 8].view(torch.float64).reshape(ny, pitch)[:, :nx]
+        pf = ref[t, fb:fb + pitch * ny * 8].view(torch.float64).reshape(ny, pitch)[:, :nx]
+        assert torch.equal(pr, pf), t
+    assert a.steps == n
+    assert torch.equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("force", ["sc", "zc"])
+def test_adjoint_steps_equal_single_steps(force):
+    """lbm_adjoint_steps over a recorded segment: lam bitwise that of single
+    reverse steps, the parameter gradient equal to summation order."""
+    po, rho0, _, _ = case("pr", force, 48, 40)
+    n = 9
+    d = L.Domain(lib_params(po), dev(rho0))
+    st = d.new_states(n + 1)
+    d.record(st, n)
+    lam0 = dev(np.random.default_rng(7).standard_normal((9, 40, 48)))
+    ws = d.adjoint_workspace()
+    lam_a, tmp = lam0.clone(), torch.empty_like(lam0)
+    grad_a = torch.zeros(2, dtype=torch.float64, device="cuda")
+    d.adjoint_steps(st, n, lam_a, tmp, grad_a, ws)
+    lam_b, nxt = lam0.clone(), torch.empty_like(lam0)
+    grad_b = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for t in reversed(range(n)):
+        d.adjoint_step(st[t], lam_b, nxt, grad_b, ws)
+        lam_b, nxt = nxt, lam_b
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a, lam_b)
+    assert torch.allclose(grad_a, grad_b, rtol=1e-12, atol=0.0), (grad_a, grad_b)
