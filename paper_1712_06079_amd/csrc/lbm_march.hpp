@@ -4,8 +4,12 @@
 // A workgroup owns one 64-column strip of the lattice over the rows [ys, ye) of
 // one y chunk and walks down it in blocks of TY rows.  Compared with
 // independent tiles (lbm_fused.hpp) this collides every row once, reads the
-// potential rows of the y stencil once per strip, and overlaps the loads of
-// block k+1 with the arithmetic of block k.
+// potential rows of the y stencil about once per strip, and overlaps the loads
+// of block k+1 with the arithmetic of block k.
+//
+// The potential rows around the block (yb-4 .. yb+TY+3, over x0-1-R ..
+// x0+64+R) live in an LDS ring of TY+8 rows, the "bar": its rows feed the x
+// derivative of the block rows and the y windows of every column.
 //
 // The y derivative.  In the difference form of the geometric recursion (see
 // stencil_recursive) the output at row o needs the forward sum Lt_o, carried
@@ -14,30 +18,31 @@
 // Grouping the t of the TY-row blocks ahead of the current block,
 //   W_j = sum_{n<TY} r^n t_{yb+1+jTY+n}   (j = 1 .. NB),
 //   q(yb+1+TY) = sum_j r^{(j-1)TY} W_j,
-// so a column keeps a window of NB block sums (one new W per block, from the
-// TY rows that arrive NB blocks ahead) and a window of the TY+8 potential rows
-// around the block, all in registers; q inside the block is the recursion
-// over its own TY rows.  NB TY + 3 >= R keeps at least R taps for every output.
+// so a column keeps NB block sums in registers (one new W per block, from the
+// TY rows that arrive NB blocks ahead) and reads the TY+8 rows around the
+// block from the bar; q inside the block is the recursion over its own TY
+// rows.  NB TY + 3 >= R keeps at least R taps for every output.
 //
 // Lanes (256 threads, four wavefronts):
-//  wave 0   one interior column each (x0 .. x0+63): d/dy -> Fy in LDS;
+//  wave 0   one interior column each (x0 .. x0+63): d/dy -> F_y in LDS;
 //  wave 1   lanes 0 .. 2TY-1 own the ring cells (columns x0-1 and x0+64, TY
-//           rows): their d/dy, an explicit d/dx over the x bar, and their
+//           rows): their d/dy, an explicit d/dx over the bar, and their
 //           collision, all during the force phase;
 //  waves 2-3  d/dx of the interior: per row and 8-column segment one lane runs
-//           the forward and its neighbour the backward recursion in lockstep
-//           (or the explicit window on a short x axis);
-//  all      one interior cell each for collision (forces combined from the
-//           partial sums) and streaming.
+//           the forward and its neighbour the backward recursion in lockstep,
+//           the two exchange their sums and each finishes half the segment's
+//           F_x (or the explicit window on a short x axis);
+//  all      one interior cell pair each for collision and streaming.
 // Per block (collision rows yb .. yb+TY-1, yb = ys - 1 + k TY):
-//  1  issue the loads of block k+1 (ring-cell populations, x bar, the new
-//     potential rows of each column); its interior populations follow in 4;
+//  1  issue the loads of block k+1 (its new bar rows, its ring-cell
+//     populations, each column's rows NB blocks ahead); its interior
+//     populations follow in 4;
 //  2  forces (and the ring cells' collision);
 //  3  collision of the interior cells into the post-collision ring (rows
 //     yb-2 .. yb+TY-1);
-//  4  commit the loads of step 1 (LDS, register windows), issue the next
-//     block's interior populations, then pull streaming of rows yb-1 ..
-//     yb+TY-2 (stored when inside [ys, ye)) and rho -> U -> phi_{t+1}.
+//  4  commit the loads of step 1 (LDS, block sums), issue the next block's
+//     interior populations, then pull streaming of rows yb-1 .. yb+TY-2
+//     (stored when inside [ys, ye)) and rho -> U -> phi_{t+1}.
 #pragma once
 
 #include "lbm_fused.hpp"
@@ -52,27 +57,27 @@ struct MarchShape {
     static constexpr int NP = (NPAIR + NT - 1) / NT;        // pairs per thread
     static constexpr int PR = TY + 2;                       // post-collision rows yb-2 .. yb+TY-1
     static constexpr int NB = (R - 3 + TY - 1) / TY;        // block sums ahead (NB TY + 3 >= R)
-    static constexpr int WIN = TY + 8;                      // potential rows yb-4 .. yb+TY+3
+    static constexpr int BR = TY + 8;                       // bar rows yb-4 .. yb+TY+3
     static constexpr int NRING = 2 * TY;                    // ring cells per block
     static constexpr int K = 4;                             // outputs per explicit-window item
     static constexpr int NSEG = 8, SEG = BX / NSEG;         // recursive x segments per row, width
-    static constexpr int RW = (CW + 2 * R) | 1;             // x-bar pitch (odd: spreads LDS banks)
-    static constexpr int NU = FORCE == FORCE_HYBRID ? 2 : 1;  // operands per difference
-    static constexpr int BAR_D = TY * RW;
-    static constexpr int PART_D = TY * BX;                  // one [TY][64] partial-sum array
+    static constexpr int RW = (CW + 2 * R) | 1;             // bar pitch (odd: spreads LDS banks)
+    static constexpr int BAR_D = BR * RW;
+    static constexpr int F_D = 2 * TY * BX;                 // F_x, F_y of the interior
     static constexpr int FRING_D = (NRING * Q * (int)sizeof(Real) + 7) / 8;
     static constexpr int POST_D = (Q * PR * CWP * (int)sizeof(Real) + 7) / 8;
     static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue staging
     static constexpr int SCR_D = POST_D > WARM_ROWS * CW ? (POST_D > WSUM_ROWS * CW ? POST_D : WSUM_ROWS * CW)
                                                          : (WARM_ROWS * CW > WSUM_ROWS * CW ? WARM_ROWS * CW
                                                                                            : WSUM_ROWS * CW);
-    static constexpr int DOUBLES = BAR_D + 2 * NU * PART_D + PART_D + FRING_D + SCR_D;
+    static constexpr int DOUBLES = BAR_D + F_D + FRING_D + SCR_D;
     static constexpr int XBASE = 2 * BX;                    // first x lane
     static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
-    static_assert((BAR_D + 2 * NU * PART_D + PART_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
+    static_assert((BAR_D + F_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
     static_assert(2 * TY * NSEG <= NT - XBASE && TY * (BX / K) <= NT - XBASE, "x lanes must fit");
     static_assert(NRING * Q <= NT, "ring-cell loads: one value per thread");
+    static_assert(SEG % 2 == 0, "each lane of a pair finishes half a segment");
 };
 
 // Interior cells are handled in pairs (x, x+1), x even, one pair per lane, so
@@ -86,18 +91,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     constexpr int R = Radius<Real>::value;
     using M = MarchShape<Real, FORCE, TY, R>;
     using V2 = Real __attribute__((ext_vector_type(2)));
-    constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, WIN = M::WIN, SEG = M::SEG;
+    constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, BR = M::BR, SEG = M::SEG;
     constexpr bool HYB = FORCE == FORCE_HYBRID;
     __shared__ __align__(16) double sm[M::DOUBLES];
     __shared__ double ctab[TAB];               // sign-folded x coefficients (staged in the prologue)
-    double* bar = sm;                          // [TY][RW] phi of the block rows, x0-1-R .. x0+64+R
-    double* Lx = bar + M::BAR_D;               // [TY][64] forward x sums (or the explicit d/dx)
-    double* Qx = Lx + M::PART_D;               // [TY][64] backward x sums
-    double* Lxu = Qx + M::PART_D;              // hybrid: the same for U = phi |phi|
-    double* Qxu = Lxu + (HYB ? M::PART_D : 0);
-    double* Fy = Qxu + (HYB ? M::PART_D : 0);  // [TY][64] y force of the interior
-    Real* fring = reinterpret_cast<Real*>(Fy + M::PART_D);                  // [2TY][Q] ring-cell f
-    double* scr = Fy + M::PART_D + M::FRING_D;                              // prologue staging
+    double* bar = sm;                          // [BR][RW] phi rows, x0-1-R .. x0+64+R; row y in slot bslot(y)
+    double* Fx = bar + M::BAR_D;               // [TY][64] x force of the interior
+    double* Fy = Fx + TY * BX;                 // [TY][64] y force of the interior
+    Real* fring = reinterpret_cast<Real*>(Fy + TY * BX);                    // [2TY][Q] ring-cell f
+    double* scr = Fy + TY * BX + M::FRING_D;                                // prologue staging
     Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CWP]
 
     const int tid = threadIdx.x, lane = tid & (BX - 1), wave = tid >> 6;
@@ -110,8 +112,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     const int nblk = (ye - ys + 2 + TY - 1) / TY;
 
     // Every row index used below lies in [ys - R - 2, ye + (NB + 2) TY + 4],
-    // within one period of [0, ny) (ny > 2R + 1): one correction wraps it.
+    // within one period of [0, ny): one correction wraps it.
     auto wrapy = [&](int y) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); };
+    // Ring slots (the smallest bar row is ys - 5, the smallest post-collision
+    // row ys - 3, so both arguments are >= 0).
+    auto bslot = [&](int y) { return (int)((unsigned)(y - ys + 16) % (unsigned)BR); };
     auto pslot = [&](int y) { return (int)((unsigned)(y - ys + 3) % (unsigned)PR); };
     auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
     auto opu = [](double v) { return v * fabs(v); };
@@ -127,26 +132,31 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // is row t / 32, cells x0 + 2 (t % 32) and the one after.
 
     // ---------------------------------------------------------------- state
-    double win[WIN];                  // phi of rows yb-4 .. yb+TY+3, this lane's column
     double W[NB], Wu[NB];             // block sums W_1 .. W_NB
     double uprev = 0.0, uprevu = 0.0; // operand of the row preceding the next far rows
     double l = 0.0, lu = 0.0;         // forward y state
-    double pnear[TY], pfar[TY];       // loads of the next block's column rows
-    StageRegs<TY * RW> sbar;          // loads of the next block's x bar
+    double pfar[TY];                  // loads of the rows NB blocks ahead (this lane's column)
+    StageRegs<TY * RW> sbar;          // loads of the bar rows entering the ring
     double fr = 0.0;                  // one ring-cell population (tid < 2 TY Q)
     Real fc[M::NP][2][Q];             // interior populations (loaded one phase 4 ahead)
 
-    auto issue = [&](int yn) {        // potential and ring-cell loads of block yn
+    // Loads of block yn (all unconditional; lanes with no use load a clamped
+    // valid address) and their commit.
+    auto issue_bar = [&](int yn) {    // bar rows yn+4 .. yn+TY+3 enter the ring for block yn
         stage_issue(sbar, [&](int i) {
             const int r = i / RW, c = i - r * RW;
-            return a.phi_in[(long)wrapy(yn + r) * pitch + wrap(x0 - 1 - R + c, nx)];
+            return a.phi_in[(long)wrapy(yn + 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
         });
-        {
-            const int i = min(tid, M::NRING * Q - 1);  // past the end: a duplicate, not stored
-            const int e = i / Q, q = i - e * Q;
-            const int xr = wrap(e < TY ? x0 - 1 : x0 + BX, nx);
-            fr = (double)a.f_in[fidx(xr, wrapy(yn + e % TY), q, nxb)];
-        }
+    };
+    auto issue_fr = [&](int yn) {     // ring-cell populations of block yn
+        const int i = min(tid, M::NRING * Q - 1);  // past the end: a duplicate, not stored
+        const int e = i / Q, q = i - e * Q;
+        const int xr = wrap(e < TY ? x0 - 1 : x0 + BX, nx);
+        fr = (double)a.f_in[fidx(xr, wrapy(yn + e % TY), q, nxb)];
+    };
+    auto issue_col = [&](int yn) {    // rows NB blocks ahead of block yn (every lane; waves 2-3 unused)
+#pragma unroll
+        for (int j = 0; j < TY; ++j) pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
     };
     // The interior populations and the new state are touched once per step:
     // non-temporal accesses keep them from evicting the potential rows, which
@@ -174,14 +184,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             }
         }
     };
-    auto issue_col = [&](int yn) {    // new window rows yn+4 .. and far rows of block yn
-        // (every lane loads; lanes of wavefronts 2-3 load a ring column they do not use)
-#pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            pnear[j] = a.phi_in[(long)wrapy(yn + 4 + j) * pitch + xcol];
-            pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
-        }
-    };
     // New block sum from the operands of rows uprev, p[0 .. TY-1]:
     // t_n = r^4 (u_{n+1} - u_n) over that row sequence, W = sum r^n t_n.
     auto block_sum = [&](double u0, const double (&p)[TY], bool hyb) {
@@ -194,12 +196,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         }
         return w;
     };
-    auto commit_col = [&]() {         // advance the column windows by one block
+    auto commit_col = [&]() {         // advance the block sums by one block
         if (colw) {
-#pragma unroll
-            for (int j = 0; j < WIN - TY; ++j) win[j] = win[j + TY];
-#pragma unroll
-            for (int j = 0; j < TY; ++j) win[WIN - TY + j] = pnear[j];
 #pragma unroll
             for (int j = 0; j < NB - 1; ++j) W[j] = W[j + 1];
             W[NB - 1] = block_sum(uprev, pfar, false);
@@ -212,18 +210,32 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             }
         }
     };
-    auto commit = [&]() {             // the next block's bar and ring cells into LDS
-        stage_commit(bar, sbar);
+    auto commit = [&](int yn) {       // block yn's new bar rows and ring cells into LDS
+#pragma unroll
+        for (int j = 0; j < StageRegs<TY * RW>::PER; ++j) {
+            const int i = tid + j * NT;
+            if (i < TY * RW) {
+                const int r = i / RW, c = i - r * RW;
+                bar[bslot(yn + 4 + r) * RW + c] = sbar.v[j];
+            }
+        }
         if (tid < M::NRING * Q) fring[tid] = (Real)fr;
     };
 
-    // d/dy of this lane's column over the block rows from its windows (lane
-    // state only): g[o], gu[o] for rows yb+o.  Advances the forward state.
-    // Window index of row y: y - (yb - 4).
+    // d/dy of this lane's column over the block rows yb .. yb+TY-1 from the
+    // bar rows yb-4 .. yb+TY+3 and the block sums: g[o], gu[o] for row yb+o,
+    // phc[o] its potential.  Advances the forward state.
     double rT = 1.0;  // r^TY
 #pragma unroll
     for (int j = 0; j < TY; ++j) rT *= rr;
-    auto ddy = [&](double (&g)[TY], double (&gu)[TY]) {
+    auto ddy = [&](int yb, double (&g)[TY], double (&gu)[TY], double (&phc)[TY]) {
+        double win[TY + 8];           // phi of rows yb-4 .. yb+TY+3 (window index of row y: y - yb + 4)
+        const int sb = bslot(yb - 4);
+#pragma unroll
+        for (int j = 0; j < TY + 8; ++j) {
+            const int s = sb + j;
+            win[j] = bar[(s >= BR ? s - BR : s) * RW + R + ccol];
+        }
         double Lt[TY], Ltu[TY];
 #pragma unroll
         for (int o = 0; o < TY; ++o) {  // forward update at row yb+o-1 reads rows yb+o-3, yb+o-4
@@ -247,6 +259,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             const int w = o + 4;
             g[o] = rd1 * (op(win[w + 1]) - op(win[w - 1])) + rd2 * (op(win[w + 2]) - op(win[w - 2])) +
                    rK * (rr3 * (op(win[w + 3]) - op(win[w - 3])) + q + Lt[o]);
+            phc[o] = win[w];
             if (HYB) {
                 qu = fma(rr, qu, rr4 * (opu(win[o + 8]) - opu(win[o + 7])));
                 gu[o] = rd1 * (opu(win[w + 1]) - opu(win[w - 1])) + rd2 * (opu(win[w + 2]) - opu(win[w - 2])) +
@@ -260,8 +273,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // ------------------------------------------------------------- prologue
     // Forward y state up to the first block (updates at rows yb0-(R-3) ..
     // yb0-2 read rows yb0-R .. yb0-4), the block sums W_1 .. W_NB of block 0
-    // (rows yb0+3+TY .. yb0+3+(NB+1)TY) and the window (rows yb0-4 ..
-    // yb0+TY+3); rows are staged in the post-collision area.
+    // (rows yb0+3+TY .. yb0+3+(NB+1)TY), staged in the post-collision area, and
+    // the bar rows yb0-4 .. yb0+TY+3.
     auto stage_rows = [&](int ylo, int nrows) {
         const int n = nrows * CW;
         for (int i0 = 0; i0 < n; i0 += 8 * NT) {
@@ -279,12 +292,28 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             }
         }
     };
-    if (colw) {
-#pragma unroll
-        for (int j = 0; j < WIN; ++j) win[j] = a.phi_in[(long)wrapy(yb0 - 4 + j) * pitch + xcol];
-    }
     stage_rows(yb0 - R, M::WARM_ROWS);
     for (int i = tid; i < TAB; i += NT) ctab[i] = a.tab->tx_tab[i];
+    {
+        const int n = M::BAR_D;
+        for (int i0 = 0; i0 < n; i0 += 8 * NT) {
+            double v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = min(i0 + tid + j * NT, n - 1);
+                const int r = i / RW, c = i - r * RW;
+                v[j] = a.phi_in[(long)wrapy(yb0 - 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = i0 + tid + j * NT;
+                if (i < n) {
+                    const int r = i / RW, c = i - r * RW;
+                    bar[bslot(yb0 - 4 + r) * RW + c] = v[j];
+                }
+            }
+        }
+    }
     __syncthreads();
     if (colw) {
         for (int m = 1; m <= R - 4; ++m) {
@@ -311,9 +340,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         uprevu = opu(last);
     }
     __syncthreads();
-    issue(yb0);
+    issue_fr(yb0);
     issue_f(yb0);
-    commit();
+    if (tid < M::NRING * Q) fring[tid] = (Real)fr;
     __syncthreads();
 
     // ------------------------------------------------------------ the march
@@ -324,31 +353,32 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     for (int k = 0; k < nblk; ++k) {
         const int yb = yb0 + k * TY;
         issue_col(yb + TY);
-        issue(yb + TY);
+        issue_bar(yb + TY);
+        issue_fr(yb + TY);
 
         // Phase 2: forces; the ring cells are also collided here.
         if (wave == 0) {
-            double g[TY], gu[TY];
-            ddy(g, gu);
+            double g[TY], gu[TY], phc[TY];
+            ddy(yb, g, gu, phc);
 #pragma unroll
-            for (int o = 0; o < TY; ++o) Fy[o * BX + lane] = force_from<FORCE>(win[o + 4], g[o], gu[o], a.A);
+            for (int o = 0; o < TY; ++o) Fy[o * BX + lane] = force_from<FORCE>(phc[o], g[o], gu[o], a.A);
         } else if (wave == 1) {
-            double g[TY], gu[TY];
-            ddy(g, gu);
+            double g[TY], gu[TY], phc[TY];
+            ddy(yb, g, gu, phc);
             if (lane < M::NRING) {
-                double gy = 0.0, gyu = 0.0, phic = 0.0;
+                double gy = 0.0, gyu = 0.0;
 #pragma unroll
                 for (int o = 0; o < TY; ++o)
                     if (o == rrow) {
                         gy = g[o];
                         gyu = gu[o];
-                        phic = win[o + 4];
                     }
                 // explicit d/dx of the ring cell over the bar: on a long x axis
                 // the row is geometric (d_n = C r^n, n >= 3) and its weights are
                 // generated in registers (four interleaved chains); a short axis
                 // uses the periodic row's table
-                const double* br = bar + rrow * RW + ccol + R;
+                const double* br = bar + bslot(yb + rrow) * RW + ccol + R;
+                const double phic = br[0];
                 double sx[4] = {0.0, 0.0, 0.0, 0.0}, sxu[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums
                 if (a.rec_x) {
                     double w[4];
@@ -358,11 +388,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                     w[3] = w[2] * rr;
 #pragma unroll 4
                     for (int n = 3; n <= R; ++n) {
-                        const int k = (n - 3) & 3;
+                        const int k4 = (n - 3) & 3;
                         const double vp = br[n], vm = br[-n];
-                        sx[k] = fma(w[k], op(vp) - op(vm), sx[k]);
-                        if (HYB) sxu[k] = fma(w[k], opu(vp) - opu(vm), sxu[k]);
-                        w[k] *= rr4;
+                        sx[k4] = fma(w[k4], op(vp) - op(vm), sx[k4]);
+                        if (HYB) sxu[k4] = fma(w[k4], opu(vp) - opu(vm), sxu[k4]);
+                        w[k4] *= rr4;
                     }
                     sx[0] = fma(rd1, op(br[1]) - op(br[-1]), sx[0]);
                     sx[1] = fma(rd2, op(br[2]) - op(br[-2]), sx[1]);
@@ -397,13 +427,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             // forward (even lane) and backward (odd lane) x recursion of one
             // 8-column segment of one row, in lockstep: at step j both read
             // u[pa] - u[pa - 1], pa = A0 + S j; the last SEG steps give the
-            // outputs o = B0 + S j, kept in registers and stored after the loop
-            // (no LDS store inside the loop, so its loads can run ahead).
+            // outputs (forward: o = m, backward: o = SEG-1-m at step R-4+m),
+            // kept in registers.  The two lanes then swap their sums and each
+            // finishes F_x of half the segment.
             const int xi = tid - M::XBASE;
             if (xi < 2 * TY * M::NSEG) {
                 const int item = xi >> 1, dir = xi & 1;
                 const int r = item % TY, sg = item / TY;
-                const double* base = bar + r * RW + R + 1 + sg * SEG;  // interior column 1 + sg SEG at k = 0
+                const double* rowp = bar + bslot(yb + r) * RW;
+                const double* base = rowp + R + 1 + sg * SEG;  // interior column 1 + sg SEG at k = 0
                 const int A0 = dir ? SEG + R - 1 : -(R - 1), S = dir ? -1 : 1;
                 double acc = 0.0, accu = 0.0, out[SEG], outu[SEG];
 #pragma unroll 8
@@ -422,14 +454,24 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                     out[m] = acc;
                     outu[m] = accu;
                 }
-                // step j = R-4+m gives output o = m (forward) or SEG-1-m (backward)
-                double* dst = (dir ? Qx : Lx) + r * BX + sg * SEG;
-                double* dstu = (dir ? Qxu : Lxu) + r * BX + sg * SEG;
+                // Lane pairs swap: for k < SEG/2 a lane receives its partner's
+                // out[k] and adds its own out[SEG-1-k]; that is the full sum at
+                // output o = SEG-1-k (forward lane) or o = k (backward lane).
 #pragma unroll
-                for (int m = 0; m < SEG; ++m) {
-                    const int o = dir ? SEG - 1 - m : m;
-                    dst[o] = out[m];
-                    if (HYB) dstu[o] = outu[m];
+                for (int k = 0; k < SEG / 2; ++k) {
+                    const double s = out[SEG - 1 - k] + __shfl_xor(out[k], 1);
+                    double su = 0.0;
+                    if (HYB) su = outu[SEG - 1 - k] + __shfl_xor(outu[k], 1);
+                    const int o = dir ? k : SEG - 1 - k;
+                    const int cc = 1 + sg * SEG + o;
+                    const double* b = rowp + cc + R;
+                    const double gx = rd1 * (op(b[1]) - op(b[-1])) + rd2 * (op(b[2]) - op(b[-2])) +
+                                      rK * (rr3 * (op(b[3]) - op(b[-3])) + s);
+                    double gxu = 0.0;
+                    if (HYB)
+                        gxu = rd1 * (opu(b[1]) - opu(b[-1])) + rd2 * (opu(b[2]) - opu(b[-2])) +
+                              rK * (rr3 * (opu(b[3]) - opu(b[-3])) + su);
+                    Fx[r * BX + cc - 1] = force_from<FORCE>(b[0], gx, gxu, a.A);
                 }
             }
         } else {
@@ -437,12 +479,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
             const int xi = tid - M::XBASE;
             if (xi < TY * (BX / M::K)) {
                 const int r = xi % TY, sg = xi / TY;
+                const double* rowp = bar + bslot(yb + r) * RW;
                 double acc[M::K], accu[M::K];
-                stencil_window<FORCE, M::K, R>(bar + r * RW + 1 + sg * M::K, 1, ctab, acc, accu);
+                stencil_window<FORCE, M::K, R>(rowp + 1 + sg * M::K, 1, ctab, acc, accu);
 #pragma unroll
                 for (int j = 0; j < M::K; ++j) {
-                    Lx[r * BX + sg * M::K + j] = acc[j];
-                    if (HYB) Lxu[r * BX + sg * M::K + j] = accu[j];
+                    const int cc = 1 + sg * M::K + j;
+                    Fx[r * BX + cc - 1] = force_from<FORCE>(rowp[cc + R], acc[j], accu[j], a.A);
                 }
             }
         }
@@ -458,25 +501,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                 double g[2][Q];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int lx = lx0 + h, c = r * BX + lx;
-                    const double* br = bar + r * RW + lx + 1 + R;
-                    double gx, gxu = 0.0;
-                    if (a.rec_x) {
-                        gx = rd1 * (op(br[1]) - op(br[-1])) + rd2 * (op(br[2]) - op(br[-2])) +
-                             rK * (rr3 * (op(br[3]) - op(br[-3])) + Qx[c] + Lx[c]);
-                        if (HYB)
-                            gxu = rd1 * (opu(br[1]) - opu(br[-1])) + rd2 * (opu(br[2]) - opu(br[-2])) +
-                                  rK * (rr3 * (opu(br[3]) - opu(br[-3])) + Qxu[c] + Lxu[c]);
-                    } else {
-                        gx = Lx[c];
-                        if (HYB) gxu = Lxu[c];
-                    }
-                    const double Fxc = force_from<FORCE>(br[0], gx, gxu, a.A);
+                    const int c = r * BX + lx0 + h;
 #pragma unroll
                     for (int q = 0; q < Q; ++q) g[h][q] = (double)fc[i][h][q];
                     double rho, jx, jy;
                     moments(g[h], rho, jx, jy);
-                    collide(g[h], rho, jx, jy, Fxc, Fy[c], a.omega);
+                    collide(g[h], rho, jx, jy, Fx[c], Fy[c], a.omega);
                 }
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {  // columns lx0+1, lx0+2 at post index lx0+2 (aligned pair)
@@ -489,10 +519,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         }
         __syncthreads();
 
-        // Phase 4 begins by committing the loads of step 1 (the bar and ring
-        // cells are not read again in this block; the windows are lane state),
-        // then loads the next block's populations and streams.
-        commit();
+        // Phase 4 begins by committing the loads of step 1 (the bar rows they
+        // replace and the ring cells are not read again in this block; the
+        // block sums are lane state), then loads the next block's populations
+        // and streams.
+        commit(yb + TY);
         commit_col();
         __builtin_amdgcn_sched_barrier(0);  // the commit's waits stay ahead of the new loads and stores
         issue_f(yb + TY);
