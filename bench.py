@@ -445,7 +445,7 @@ def main():
                     help="0 automatic (strip march here), 1 two-pass reference, 2 fused tiles, 3 fused strip march")
     ap.add_argument("--tile", type=int, default=0, help="rows per tile or marching block (0 = default)")
     ap.add_argument("--chunks", type=int, default=0, help="y chunks per strip of the marching kernel (0 = automatic)")
-    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle sample steps (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=64, help="oracle sample steps (0 = skip)")
     ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-probe", action="store_true", help="only run the streaming-copy calibration kernel")
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
