@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
 SOURCES = ["lbm_api.hip", "lbm_batch.hip", "eos_host.cpp", "hdm_coeffs.cpp"]
-HEADERS = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_fused.hpp", "lbm_adjoint.hpp", "lbm_internal.hpp", "eos_host.hpp", "hdm_coeffs.hpp"]
+HEADERS = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_fused.hpp", "lbm_march.hpp", "lbm_adjoint.hpp", "lbm_internal.hpp", "eos_host.hpp", "hdm_coeffs.hpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -34,15 +34,16 @@
 //           F_x (or the explicit window on a short x axis);
 //  all      one interior cell pair each for collision and streaming.
 // Per block (collision rows yb .. yb+TY-1, yb = ys - 1 + k TY):
-//  1  issue the loads of block k+1 (its new bar rows, its ring-cell
-//     populations, each column's rows NB blocks ahead); its interior
-//     populations follow in 4;
 //  2  forces (and the ring cells' collision);
-//  3  collision of the interior cells into the post-collision ring (rows
-//     yb-2 .. yb+TY-1);
-//  4  commit the loads of step 1 (LDS, block sums), issue the next block's
-//     interior populations, then pull streaming of rows yb-1 .. yb+TY-2
-//     (stored when inside [ys, ye)) and rho -> U -> phi_{t+1}.
+//  3  issue the loads of block k+1 (its new bar rows, its ring-cell
+//     populations, each column's rows NB blocks ahead), then collide the
+//     interior cells into the post-collision ring (rows yb-2 .. yb+TY-1);
+//  4  commit the loads of step 3 (LDS, block sums), issue the next block's
+//     interior populations (in flight through the next block's step 2),
+//     then pull streaming of rows yb-1 .. yb+TY-2 (stored when inside
+//     [ys, ye)) and rho -> U -> phi_{t+1}.
+// Issuing the step-3 loads after the force phase keeps their registers out
+// of that phase, the kernel's register peak.
 #pragma once
 
 #include "lbm_fused.hpp"
@@ -72,6 +73,10 @@ struct MarchShape {
                                                                                            : WSUM_ROWS * CW);
     static constexpr int DOUBLES = BAR_D + F_D + FRING_D + SCR_D;
     static constexpr int XBASE = 2 * BX;                    // first x lane
+    // Waves per SIMD the register allocation must allow: three for FP32
+    // populations (their LDS footprint admits three workgroups per CU), two
+    // otherwise (FP64 rows take more LDS; the hybrid force more registers).
+    static constexpr int WAVES = (sizeof(Real) == 4 && FORCE != FORCE_HYBRID) ? 3 : 2;
     static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
     static_assert((BAR_D + F_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
@@ -84,10 +89,10 @@ struct MarchShape {
 // that a lane moves both cells' populations with one 16-byte (FP64) or 8-byte
 // (FP32) access.  VEC selects those paired accesses; it requires an even N_x
 // (a pair never straddles the periodic seam).  Odd N_x uses per-cell accesses.
-// At least two waves per SIMD (two workgroups per CU): the register budget
-// (VGPRs + AGPRs <= 256) is a hard limit, not a hint.
+// The register budget follows MarchShape::WAVES (VGPRs + AGPRs <= 512 / WAVES);
+// it is a hard limit, not a hint.
 template <typename Real, int FORCE, int TY, bool VEC>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_march(StepArgs<Real> a, int nchunk) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchShape<Real, FORCE, TY, Radius<Real>::value>::WAVES))) k_march(StepArgs<Real> a, int nchunk) {
     constexpr int R = Radius<Real>::value;
     using M = MarchShape<Real, FORCE, TY, R>;
     using V2 = Real __attribute__((ext_vector_type(2)));
@@ -102,7 +107,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     double* scr = Fy + TY * BX + M::FRING_D;                                // prologue staging
     Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CWP]
 
-    const int tid = threadIdx.x, lane = tid & (BX - 1), wave = tid >> 6;
+    // Lane-dependent indices are re-derived in every block from a copy of the
+    // thread index that the compiler cannot treat as loop-invariant: hoisting
+    // the many lane-dependent offsets out of the march would hold them in
+    // registers for the whole kernel.  Only the wrapped lattice columns that
+    // need a general modulo are kept (bcol, xcol, xring, xpair).
+    int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    int lane = tid & (BX - 1);
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int chunk = t / nxb, strip = t - chunk * nxb;
@@ -125,9 +137,29 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // Column owned by this lane (waves 0-1): interior column x0+lane, or the
     // ring column of ring lane e = lane (x0-1 for e < TY, x0+64 otherwise).
     const bool colw = wave < 2;
-    const int ccol = wave == 0 ? lane + 1 : (lane < TY ? 0 : CW - 1);   // collision column
-    const long xcol = wrap(x0 - 1 + ccol, nx);
-    const int rrow = lane % TY;                                           // ring lane's row
+    int ccol = wave == 0 ? lane + 1 : (lane < TY ? 0 : CW - 1);   // collision column
+    int rrow = lane % TY;                                         // ring lane's row
+    auto lane_indices = [&]() {
+        lane = tid & (BX - 1);
+        ccol = wave == 0 ? lane + 1 : (lane < TY ? 0 : CW - 1);
+        rrow = lane % TY;
+    };
+    const int xcol = wrap(x0 - 1 + ccol, nx);
+    constexpr int BPER = StageRegs<TY * RW>::PER;
+    int bcol[BPER];                   // lattice column of each bar element this thread loads
+#pragma unroll
+    for (int j = 0; j < BPER; ++j) {
+        const int i = min(tid + j * NT, TY * RW - 1);
+        bcol[j] = wrap(x0 - 1 - R + (i - (i / RW) * RW), nx);
+    }
+    const int xring = wrap(min(tid, M::NRING * Q - 1) / Q < TY ? x0 - 1 : x0 + BX, nx);
+    int xpair[M::NP][2];              // lattice columns of this thread's interior pairs
+#pragma unroll
+    for (int i = 0; i < M::NP; ++i) {
+        const int t = min(tid + i * NT, M::NPAIR - 1);
+        xpair[i][0] = wrap(x0 + 2 * (t & 31), nx);
+        xpair[i][1] = VEC ? 0 : wrap(x0 + 2 * (t & 31) + 1, nx);
+    }
     // Interior pairs of this thread (collision and streaming): pair t = tid + i NT
     // is row t / 32, cells x0 + 2 (t % 32) and the one after.
 
@@ -143,16 +175,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // Loads of block yn (all unconditional; lanes with no use load a clamped
     // valid address) and their commit.
     auto issue_bar = [&](int yn) {    // bar rows yn+4 .. yn+TY+3 enter the ring for block yn
-        stage_issue(sbar, [&](int i) {
-            const int r = i / RW, c = i - r * RW;
-            return a.phi_in[(long)wrapy(yn + 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
-        });
+#pragma unroll
+        for (int j = 0; j < BPER; ++j) {
+            const int i = min(tid + j * NT, TY * RW - 1);  // past the end: a duplicate, not stored
+            sbar.v[j] = a.phi_in[(long)wrapy(yn + 4 + i / RW) * pitch + bcol[j]];
+        }
     };
     auto issue_fr = [&](int yn) {     // ring-cell populations of block yn
         const int i = min(tid, M::NRING * Q - 1);  // past the end: a duplicate, not stored
         const int e = i / Q, q = i - e * Q;
-        const int xr = wrap(e < TY ? x0 - 1 : x0 + BX, nx);
-        fr = (double)a.f_in[fidx(xr, wrapy(yn + e % TY), q, nxb)];
+        fr = (double)a.f_in[fidx(xring, wrapy(yn + e % TY), q, nxb)];
     };
     auto issue_col = [&](int yn) {    // rows NB blocks ahead of block yn (every lane; waves 2-3 unused)
 #pragma unroll
@@ -166,7 +198,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         for (int i = 0; i < M::NP; ++i) {
             const int t = min(tid + i * NT, M::NPAIR - 1);  // past the end: a duplicate, never used
             const int yw = wrapy(yn + (t >> 5));
-            const int xa = wrap(x0 + 2 * (t & 31), nx);
+            const int xa = xpair[i][0];
             if (VEC) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
@@ -175,7 +207,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
                     fc[i][1][q] = v.y;
                 }
             } else {
-                const int xb = wrap(x0 + 2 * (t & 31) + 1, nx);
+                const int xb = xpair[i][1];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     fc[i][0][q] = __builtin_nontemporal_load(a.f_in + fidx(xa, yw, q, nxb));
@@ -352,9 +384,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     // needs, not the younger prefetches.
     for (int k = 0; k < nblk; ++k) {
         const int yb = yb0 + k * TY;
-        issue_col(yb + TY);
-        issue_bar(yb + TY);
-        issue_fr(yb + TY);
+        asm volatile("" : "+v"(tid));
+        lane_indices();
 
         // Phase 2: forces; the ring cells are also collided here.
         if (wave == 0) {
@@ -491,7 +522,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         }
         __syncthreads();
 
-        // Phase 3: collision of the interior cells, two per lane.
+        issue_col(yb + TY);
+        issue_bar(yb + TY);
+        issue_fr(yb + TY);
+        // Phase 3: loads of the next block, then the collision of the interior
+        // cells, two per lane.
 #pragma unroll
         for (int i = 0; i < M::NP; ++i) {
             const int t = tid + i * NT;
@@ -519,7 +554,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
         }
         __syncthreads();
 
-        // Phase 4 begins by committing the loads of step 1 (the bar rows they
+        // Phase 4 begins by committing the loads of step 3 (the bar rows they
         // replace and the ring cells are not read again in this block; the
         // block sums are lane state), then loads the next block's populations
         // and streams.
