@@ -95,19 +95,41 @@ __device__ inline double feq(int i, double rho, double ux, double uy, double usq
 
 // BGK collision with Kupershtokh's exact-difference forcing (Eqs. 1, 10):
 //   f*_i = f_i - (f_i - f^eq_i(u)) / tau + f^eq_i(u + F/rho) - f^eq_i(u)
-//        = (1 - 1/tau) (f_i - f^eq_i(u)) + f^eq_i(u + F/rho),   u = j / rho.
+//        = k f_i + [f^eq_i(v) - k f^eq_i(u)],   k = 1 - 1/tau,
+// with u = j / rho and v = J / rho, J = j + F.  Expanding Eq. 2, the bracket
+// is w_i [B + e_i . m + e_ix^2 Txx + e_iy^2 Tyy + e_ix e_iy Txy] with
+//   B   = rho / tau - 1.5 (|J|^2 - k |j|^2) / rho,     m = 3 (J - k j),
+//   Txx = 4.5 (Jx^2 - k jx^2) / rho,   Tyy = 4.5 (Jy^2 - k jy^2) / rho,
+//   Txy = 9 (Jx Jy - k jx jy) / rho,
+// so the nine directions share the second-order terms (the same value as the
+// two equilibria written out, up to rounding order).  Every fused multiply-add
+// is explicit and the compiler may form no others, so every inlined copy of
+// the collision rounds alike (cells that start equal stay bitwise equal
+// whichever kernel path collides them).
 __device__ inline void collide(double (&f)[Q], double rho, double jx, double jy, double Fx, double Fy, double omega) {
-    double ir = 1.0 / rho;
-    double ux = jx * ir, uy = jy * ir;
-    double vx = ux + Fx * ir, vy = uy + Fy * ir;
-    double usq = ux * ux + uy * uy, vsq = vx * vx + vy * vy;
-    double keep = 1.0 - omega;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        double e0 = feq(i, rho, ux, uy, usq);
-        double e1 = feq(i, rho, vx, vy, vsq);
-        f[i] = keep * (f[i] - e0) + e1;
-    }
+#pragma clang fp contract(off)
+    const double keep = 1.0 - omega;
+    const double ir = 1.0 / rho;
+    const double Jx = jx + Fx, Jy = jy + Fy;
+    const double kx = keep * jx, ky = keep * jy;
+    const double Sxx = fma(-kx, jx, Jx * Jx), Syy = fma(-ky, jy, Jy * Jy), Sxy = fma(-kx, jy, Jx * Jy);
+    const double h = 4.5 * ir, h2 = 9.0 * ir;
+    const double B = fma(-1.5 * ir, Sxx + Syy, rho * omega);
+    const double ax = fma(h, Sxx, B), ay = fma(h, Syy, B);   // axis directions: B + Txx, B + Tyy
+    const double dd = fma(h, Syy, ax);                       // diagonals: B + Txx + Tyy
+    const double dp = fma(h2, Sxy, dd), dm = fma(-h2, Sxy, dd);   // e_x e_y = +1, -1
+    const double mx = 3.0 * (Jx - kx), my = 3.0 * (Jy - ky);
+    const double sp = mx + my, sm = mx - my;
+    const double w0 = wq<double>(0), w1 = wq<double>(1), w2 = wq<double>(5);
+    f[0] = fma(keep, f[0], w0 * B);
+    f[1] = fma(keep, f[1], w1 * (ax + mx));
+    f[3] = fma(keep, f[3], w1 * (ax - mx));
+    f[2] = fma(keep, f[2], w1 * (ay + my));
+    f[4] = fma(keep, f[4], w1 * (ay - my));
+    f[5] = fma(keep, f[5], w2 * (dp + sp));   // (1, 1)
+    f[7] = fma(keep, f[7], w2 * (dp - sp));   // (-1, -1)
+    f[8] = fma(keep, f[8], w2 * (dm + sm));   // (1, -1)
+    f[6] = fma(keep, f[6], w2 * (dm - sm));   // (-1, 1)
 }
 
 __device__ inline void moments(const double (&f)[Q], double& rho, double& jx, double& jy) {
