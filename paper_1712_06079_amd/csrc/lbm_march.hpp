@@ -26,24 +26,24 @@
 // Lanes (256 threads, four wavefronts):
 //  wave 0   one interior column each (x0 .. x0+63): d/dy -> F_y in LDS;
 //  wave 1   lanes 0 .. 2TY-1 own the ring cells (columns x0-1 and x0+64, TY
-//           rows): their d/dy, an explicit d/dx over the bar, and their
-//           collision, all during the force phase;
-//  waves 2-3  d/dx of the interior: per row and 8-column segment one lane runs
-//           the forward and its neighbour the backward recursion in lockstep,
-//           the two exchange their sums and each finishes half the segment's
-//           F_x (or the explicit window on a short x axis);
+//           rows): their d/dy in the force phase (on a short x axis also
+//           their d/dx, over the bar), their collision in the collision phase;
+//  waves 2-3  d/dx of the interior and of the ring cells: per row and 8-column
+//           segment one lane runs the forward and its neighbour the backward
+//           recursion in lockstep, the two exchange their sums and each
+//           finishes half the segment's F_x (or the explicit window on a short
+//           x axis);
 //  all      one interior cell pair each for collision and streaming.
 // Per block (collision rows yb .. yb+TY-1, yb = ys - 1 + k TY):
-//  2  forces (and the ring cells' collision);
-//  3  issue the loads of block k+1 (its new bar rows, its ring-cell
-//     populations, each column's rows NB blocks ahead), then collide the
-//     interior cells into the post-collision ring (rows yb-2 .. yb+TY-1);
-//  4  commit the loads of step 3 (LDS, block sums), issue the next block's
+//  1  issue the loads of block k+1 (its new bar rows, its ring-cell
+//     populations, each column's rows NB blocks ahead);
+//  2  forces of the interior and of the ring cells;
+//  3  collision of the interior and ring cells into the post-collision ring
+//     (rows yb-2 .. yb+TY-1);
+//  4  commit the loads of step 1 (LDS, block sums), issue the next block's
 //     interior populations (in flight through the next block's step 2),
 //     then pull streaming of rows yb-1 .. yb+TY-2 (stored when inside
 //     [ys, ye)) and rho -> U -> phi_{t+1}.
-// Issuing the step-3 loads after the force phase keeps their registers out
-// of that phase, the kernel's register peak.
 #pragma once
 
 #include "lbm_fused.hpp"
@@ -64,7 +64,7 @@ struct MarchShape {
     static constexpr int NSEG = 8, SEG = BX / NSEG;         // recursive x segments per row, width
     static constexpr int RW = (CW + 2 * R) | 1;             // bar pitch (odd: spreads LDS banks)
     static constexpr int BAR_D = BR * RW;
-    static constexpr int F_D = 2 * TY * BX;                 // F_x, F_y of the interior
+    static constexpr int F_D = 2 * TY * BX + 2 * NRING;     // F_x, F_y of the interior and of the ring cells
     static constexpr int FRING_D = (NRING * Q * (int)sizeof(Real) + 7) / 8;
     static constexpr int POST_D = (Q * PR * CWP * (int)sizeof(Real) + 7) / 8;
     static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue staging
@@ -73,10 +73,10 @@ struct MarchShape {
                                                                                            : WSUM_ROWS * CW);
     static constexpr int DOUBLES = BAR_D + F_D + FRING_D + SCR_D;
     static constexpr int XBASE = 2 * BX;                    // first x lane
-    // Waves per SIMD the register allocation must allow: three for FP32
-    // populations (their LDS footprint admits three workgroups per CU), two
-    // otherwise (FP64 rows take more LDS; the hybrid force more registers).
-    static constexpr int WAVES = (sizeof(Real) == 4 && FORCE != FORCE_HYBRID) ? 3 : 2;
+    // Waves per SIMD the register allocation must allow (at most 512 / WAVES
+    // VGPRs): three, two for the hybrid force (two potential fields).  The LDS
+    // footprint may allow fewer (FP64 with TY = 8: two workgroups per CU).
+    static constexpr int WAVES = FORCE == FORCE_HYBRID ? 2 : 3;
     static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
     static_assert((BAR_D + F_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
@@ -103,8 +103,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     double* bar = sm;                          // [BR][RW] phi rows, x0-1-R .. x0+64+R; row y in slot bslot(y)
     double* Fx = bar + M::BAR_D;               // [TY][64] x force of the interior
     double* Fy = Fx + TY * BX;                 // [TY][64] y force of the interior
-    Real* fring = reinterpret_cast<Real*>(Fy + TY * BX);                    // [2TY][Q] ring-cell f
-    double* scr = Fy + TY * BX + M::FRING_D;                                // prologue staging
+    double* FxR = Fy + TY * BX;                // [2TY] x force of the ring cells
+    double* FyR = FxR + M::NRING;              // [2TY] y force of the ring cells
+    Real* fring = reinterpret_cast<Real*>(FyR + M::NRING);                  // [2TY][Q] ring-cell f
+    double* scr = FyR + M::NRING + M::FRING_D;                              // prologue staging
     Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CWP]
 
     // Lane-dependent indices are re-derived in every block from a copy of the
@@ -386,8 +388,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
         const int yb = yb0 + k * TY;
         asm volatile("" : "+v"(tid));
         lane_indices();
+        issue_col(yb + TY);
+        issue_bar(yb + TY);
+        issue_fr(yb + TY);
 
-        // Phase 2: forces; the ring cells are also collided here.
+        // Phase 2: forces of the interior and of the ring cells.
         if (wave == 0) {
             double g[TY], gu[TY], phc[TY];
             ddy(yb, g, gu, phc);
@@ -404,34 +409,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                         gy = g[o];
                         gyu = gu[o];
                     }
-                // explicit d/dx of the ring cell over the bar: on a long x axis
-                // the row is geometric (d_n = C r^n, n >= 3) and its weights are
-                // generated in registers (four interleaved chains); a short axis
-                // uses the periodic row's table
                 const double* br = bar + bslot(yb + rrow) * RW + ccol + R;
                 const double phic = br[0];
-                double sx[4] = {0.0, 0.0, 0.0, 0.0}, sxu[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums
-                if (a.rec_x) {
-                    double w[4];
-                    w[0] = rK * (1.0 - rr) * rr3;
-                    w[1] = w[0] * rr;
-                    w[2] = w[1] * rr;
-                    w[3] = w[2] * rr;
-#pragma unroll 4
-                    for (int n = 3; n <= R; ++n) {
-                        const int k4 = (n - 3) & 3;
-                        const double vp = br[n], vm = br[-n];
-                        sx[k4] = fma(w[k4], op(vp) - op(vm), sx[k4]);
-                        if (HYB) sxu[k4] = fma(w[k4], opu(vp) - opu(vm), sxu[k4]);
-                        w[k4] *= rr4;
-                    }
-                    sx[0] = fma(rd1, op(br[1]) - op(br[-1]), sx[0]);
-                    sx[1] = fma(rd2, op(br[2]) - op(br[-2]), sx[1]);
-                    if (HYB) {
-                        sxu[0] = fma(rd1, opu(br[1]) - opu(br[-1]), sxu[0]);
-                        sxu[1] = fma(rd2, opu(br[2]) - opu(br[-2]), sxu[1]);
-                    }
-                } else {
+                FyR[lane] = force_from<FORCE>(phic, gy, gyu, a.A);
+                if (!a.rec_x) {
+                    // d/dx of the ring cell on a short x axis: the periodic
+                    // row's table over the bar (on a long axis the x lanes
+                    // produce it with the interior)
+                    double sx[4] = {0.0, 0.0, 0.0, 0.0}, sxu[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums
 #pragma unroll 8
                     for (int n = 1; n <= R; ++n) {
                         const double c = ctab[TAB_OFF + n];
@@ -439,28 +424,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                         sx[n & 3] = fma(c, op(vp) - op(vm), sx[n & 3]);
                         if (HYB) sxu[n & 3] = fma(c, opu(vp) - opu(vm), sxu[n & 3]);
                     }
+                    const double gx = (sx[0] + sx[1]) + (sx[2] + sx[3]);
+                    const double gxu = (sxu[0] + sxu[1]) + (sxu[2] + sxu[3]);
+                    FxR[lane] = force_from<FORCE>(phic, gx, gxu, a.A);
                 }
-                const double gx = (sx[0] + sx[1]) + (sx[2] + sx[3]);
-                const double gxu = (sxu[0] + sxu[1]) + (sxu[2] + sxu[3]);
-                const double Fxr = force_from<FORCE>(phic, gx, gxu, a.A);
-                const double Fyr = force_from<FORCE>(phic, gy, gyu, a.A);
-                double g9[Q];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) g9[q] = (double)fring[lane * Q + q];
-                double rho, jx, jy;
-                moments(g9, rho, jx, jy);
-                collide(g9, rho, jx, jy, Fxr, Fyr, a.omega);
-                const int ps = pslot(yb + rrow);
-#pragma unroll
-                for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CWP + ccol + 1] = (Real)g9[q];
             }
         } else if (a.rec_x) {
             // forward (even lane) and backward (odd lane) x recursion of one
             // 8-column segment of one row, in lockstep: at step j both read
             // u[pa] - u[pa - 1], pa = A0 + S j; the last SEG steps give the
             // outputs (forward: o = m, backward: o = SEG-1-m at step R-4+m),
-            // kept in registers.  The two lanes then swap their sums and each
-            // finishes F_x of half the segment.
+            // kept in registers, in units of r^4 (the factor is applied once
+            // per output).  The two lanes then swap their sums and each
+            // finishes F_x of half the segment.  One more step past the
+            // outputs gives the ring columns: the forward sum at x0-1 is
+            // segment 0's sum before its first output, the backward sum there
+            // its backward lane's extra step, and mirrored at x0+64 for the
+            // last segment.
             const int xi = tid - M::XBASE;
             if (xi < 2 * TY * M::NSEG) {
                 const int item = xi >> 1, dir = xi & 1;
@@ -473,17 +453,24 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                 for (int j = 0; j < R - 4; ++j) {  // warm-up steps
                     const int pa = A0 + S * j;
                     const double va = base[pa], vb = base[pa - 1];
-                    acc = fma(rr, acc, rr4 * (op(va) - op(vb)));
-                    if (HYB) accu = fma(rr, accu, rr4 * (opu(va) - opu(vb)));
+                    acc = fma(rr, acc, op(va) - op(vb));
+                    if (HYB) accu = fma(rr, accu, opu(va) - opu(vb));
                 }
+                const double pre = acc, preu = accu;  // sum at the column before the outputs
 #pragma unroll
                 for (int m = 0; m < SEG; ++m) {    // output steps
                     const int pa = A0 + S * (R - 4 + m);
                     const double va = base[pa], vb = base[pa - 1];
-                    acc = fma(rr, acc, rr4 * (op(va) - op(vb)));
-                    if (HYB) accu = fma(rr, accu, rr4 * (opu(va) - opu(vb)));
+                    acc = fma(rr, acc, op(va) - op(vb));
+                    if (HYB) accu = fma(rr, accu, opu(va) - opu(vb));
                     out[m] = acc;
                     outu[m] = accu;
+                }
+                {                                  // the column after the outputs
+                    const int pa = A0 + S * (R - 4 + SEG);
+                    const double va = base[pa], vb = base[pa - 1];
+                    acc = fma(rr, acc, op(va) - op(vb));
+                    if (HYB) accu = fma(rr, accu, opu(va) - opu(vb));
                 }
                 // Lane pairs swap: for k < SEG/2 a lane receives its partner's
                 // out[k] and adds its own out[SEG-1-k]; that is the full sum at
@@ -497,12 +484,28 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                     const int cc = 1 + sg * SEG + o;
                     const double* b = rowp + cc + R;
                     const double gx = rd1 * (op(b[1]) - op(b[-1])) + rd2 * (op(b[2]) - op(b[-2])) +
-                                      rK * (rr3 * (op(b[3]) - op(b[-3])) + s);
+                                      rK * (rr3 * (op(b[3]) - op(b[-3])) + rr4 * s);
                     double gxu = 0.0;
                     if (HYB)
                         gxu = rd1 * (opu(b[1]) - opu(b[-1])) + rd2 * (opu(b[2]) - opu(b[-2])) +
-                              rK * (rr3 * (opu(b[3]) - opu(b[-3])) + su);
+                              rK * (rr3 * (opu(b[3]) - opu(b[-3])) + rr4 * su);
                     Fx[r * BX + cc - 1] = force_from<FORCE>(b[0], gx, gxu, a.A);
+                }
+                // ring cells: x0-1 (backward lane of segment 0, ring cell r)
+                // and x0+64 (forward lane of the last segment, ring cell TY+r)
+                const double s = acc + __shfl_xor(pre, 1);
+                double su = 0.0;
+                if (HYB) su = accu + __shfl_xor(preu, 1);
+                if (dir ? sg == 0 : sg == M::NSEG - 1) {
+                    const int cc = dir ? 0 : CW - 1;
+                    const double* b = rowp + cc + R;
+                    const double gx = rd1 * (op(b[1]) - op(b[-1])) + rd2 * (op(b[2]) - op(b[-2])) +
+                                      rK * (rr3 * (op(b[3]) - op(b[-3])) + rr4 * s);
+                    double gxu = 0.0;
+                    if (HYB)
+                        gxu = rd1 * (opu(b[1]) - opu(b[-1])) + rd2 * (opu(b[2]) - opu(b[-2])) +
+                              rK * (rr3 * (opu(b[3]) - opu(b[-3])) + rr4 * su);
+                    FxR[dir ? r : TY + r] = force_from<FORCE>(b[0], gx, gxu, a.A);
                 }
             }
         } else {
@@ -522,11 +525,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
         }
         __syncthreads();
 
-        issue_col(yb + TY);
-        issue_bar(yb + TY);
-        issue_fr(yb + TY);
-        // Phase 3: loads of the next block, then the collision of the interior
-        // cells, two per lane.
+        // Phase 3: collision of the interior cells, two per lane, and of the
+        // ring cells.
 #pragma unroll
         for (int i = 0; i < M::NP; ++i) {
             const int t = tid + i * NT;
@@ -552,9 +552,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                 }
             }
         }
+        if (wave == 1 && lane < M::NRING) {  // the ring cells (columns x0-1, x0+64)
+            double g9[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) g9[q] = (double)fring[lane * Q + q];
+            double rho, jx, jy;
+            moments(g9, rho, jx, jy);
+            collide(g9, rho, jx, jy, FxR[lane], FyR[lane], a.omega);
+            const int ps = pslot(yb + rrow);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) post[(q * PR + ps) * CWP + ccol + 1] = (Real)g9[q];
+        }
         __syncthreads();
 
-        // Phase 4 begins by committing the loads of step 3 (the bar rows they
+        // Phase 4 begins by committing the loads of step 1 (the bar rows they
         // replace and the ring cells are not read again in this block; the
         // block sums are lane state), then loads the next block's populations
         // and streams.
