@@ -140,7 +140,11 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     double* Fx = sm + S::A_DOUBLES;             // [CH][CW]
     double* Fy = Fx + S::NCELL;
 
-    const int tid = threadIdx.x;
+    // The thread index passes through an empty asm statement so that, in the
+    // batched kernel's loop over tiles, the compiler cannot hoist the
+    // lane-dependent offsets below out of the loop and hold them in registers.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
 
     // Phase 1 loads: the potential cross, issued first because it is needed
@@ -148,12 +152,12 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     // also wait for the populations).
     StageRegs<CH * S::RW> srow;
     StageRegs<S::VH * CW> scol;
-    stage_issue(srow, [&](int i) {
+    stage_issue(srow, tid, [&](int i) {
         const int r = i / S::RW, c = i - r * S::RW;
         const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
         return a.phi_in[(long)yw * pitch + xw];
     });
-    stage_issue(scol, [&](int i) {
+    stage_issue(scol, tid, [&](int i) {
         const int r = i / CW, c = i - r * CW;
         const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
         return a.phi_in[(long)yw * pitch + xw];
@@ -177,8 +181,8 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 1: the cross and the coefficient tables into LDS.
-    stage_commit(rowr, srow);
-    stage_commit(colr, scol);
+    stage_commit(rowr, tid, srow);
+    stage_commit(colr, tid, scol);
     for (int i = tid; i < TAB; i += NT) {
         tabs[i] = a.tab->tx_tab[i];
         tabs[TAB + i] = a.tab->ty_tab[i];

@@ -88,25 +88,25 @@ struct StageRegs {
     double v[PER];
 };
 
-// Split form of the copy: stage_issue loads every element of this thread
+// Split form of the copy: stage_issue loads every element of thread tid
 // into registers, stage_commit stores them, so other loads (issued after
 // stage_issue) do not delay the wait before the LDS stores.
 template <int N, typename Src>
-__device__ inline void stage_issue(StageRegs<N>& s, Src src) {
+__device__ inline void stage_issue(StageRegs<N>& s, int tid, Src src) {
 #pragma unroll
     for (int j = 0; j < StageRegs<N>::PER; ++j) {
         // past the end: reload the last element (kept unconditional so the
         // loads form one straight-line batch; the duplicate is not stored)
-        const int i = min((int)threadIdx.x + j * NT, N - 1);
+        const int i = min(tid + j * NT, N - 1);
         s.v[j] = src(i);
     }
 }
 
 template <int N>
-__device__ inline void stage_commit(double* __restrict__ dst, const StageRegs<N>& s) {
+__device__ inline void stage_commit(double* __restrict__ dst, int tid, const StageRegs<N>& s) {
 #pragma unroll
     for (int j = 0; j < StageRegs<N>::PER; ++j) {
-        const int i = threadIdx.x + j * NT;
+        const int i = tid + j * NT;
         if (i < N) dst[i] = s.v[j];
     }
 }
