@@ -141,6 +141,24 @@ def traffic_from_profile(kernel: str, name: str, prec: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def stream_model(kernel: str, name: str, prec: str, probe, launch_ms: float):
+    """Time the kernel's measured HBM reads and writes (committed rocprofv3
+    summary) would take at the streaming read and write rates of the probe,
+    t = reads / read rate + writes / write rate (the form a plain copy obeys
+    on this memory), and the fraction of that bound the kernel reaches."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_{prec}_pmc.json")
+    if not probe or "read" not in probe or "write" not in probe or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    rd, wr = rec["hbm_read_bytes"], rec["hbm_write_bytes"]
+    ms = rd / (probe["read"]["GBps"] * 1e6) + wr / (probe["write"]["GBps"] * 1e6)
+    return {"read_bytes": rd, "write_bytes": wr, "read_GBps": probe["read"]["GBps"],
+            "write_GBps": probe["write"]["GBps"], "model_ms": round(ms, 5), "frac_of_model": round(ms / launch_ms, 4)}
+
+
 def batch_sweep(steps: int, sep_steps: int, seed: int = 2024):
     """The coexistence sweep: 64 periodic flat-interface domains, N_x in
     {128, 256, 512}, N_y in {8, 16, 32} from the seed, 32 Peng-Robinson
@@ -287,15 +305,19 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
 
 
 def copy_probe(gib: float = 2.0, reps: int = 20, kinds=("mul",)):
-    """Plain streaming kernels of known size (FP64, `gib` GiB read and written
-    per launch): "mul" is dst = 1.0 * src (the kernel the counter calibration
-    uses), "copy" is dst.copy_(src).  Their rates are the attainable HBM
-    bandwidth the fused step is compared with."""
+    """Plain streaming kernels of known size (FP64 arrays of `gib` GiB): "mul"
+    is dst = 1.0 * src (the kernel the counter calibration uses), "copy" is
+    dst.copy_(src) (both read and write `gib` GiB), "read" is src.sum() (reads
+    only), "write" is dst.fill_(1) (writes only).  Their rates are the
+    attainable HBM bandwidth the fused step is compared with; on HBM3E reads
+    stream markedly faster than writes."""
     import torch
     n = int(gib * (1 << 30) / 8)
     src = torch.rand(n, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
-    ops = {"mul": lambda: torch.mul(src, 1.0, out=dst), "copy": lambda: dst.copy_(src)}
+    ops = {"mul": lambda: torch.mul(src, 1.0, out=dst), "copy": lambda: dst.copy_(src),
+           "read": lambda: src.sum(), "write": lambda: dst.fill_(1.0)}
+    factor = {"mul": 2, "copy": 2, "read": 1, "write": 1}
     out = {}
     for kind in kinds:
         f = ops[kind]
@@ -309,7 +331,7 @@ def copy_probe(gib: float = 2.0, reps: int = 20, kinds=("mul",)):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        moved = 2 * n * 8
+        moved = factor[kind] * n * 8
         out[kind] = {"bytes_per_launch": moved, "ms": round(ms, 4), "GBps": round(moved / (ms * 1e-3) / 1e9, 1)}
     return out
 
@@ -492,7 +514,7 @@ def main():
     droplet = droplet_report(args.droplet_steps) if args.droplet_steps > 0 else None
     long_cmp = long_run_comparison(args.long_steps) if args.long_steps > 0 and args.workload == "c5" else None
     curve = size_curve((2048, 8192), args.curve_steps) if args.curve_steps > 0 and args.workload == "c5" else None
-    probe = copy_probe(kinds=("mul", "copy")) if args.curve_steps > 0 else None
+    probe = copy_probe(kinds=("mul", "copy", "read", "write")) if args.curve_steps > 0 else None
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
     kname = KERNEL_NAMES.get(args.variant, "k_march")
     traffic = traffic_from_profile(kname, args.workload, args.prec)
@@ -523,6 +545,9 @@ def main():
         line["size_curve"] = curve
     if probe:
         line["copy_probe"] = probe
+        sm = stream_model(kname, args.workload, args.prec, probe, r["launch_ms_mean"])
+        if sm:
+            line["stream_model"] = sm
     print(json.dumps(line), flush=True)
 
 
