@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
     LBM_OK = 0,
     LBM_EINVAL = 1,        /* invalid argument: sizes < 5, tau <= 1/2, null pointer, bad enum, T >= Tc where coexistence is asked */
-    LBM_ENOMEM = 2,        /* workspace smaller than lbm_workspace_bytes() */
+    LBM_ENOMEM = 2,        /* workspace smaller than lbm_workspace_bytes(), or host memory exhausted */
     LBM_EDEVICE = 3,       /* a HIP call failed (message in lbm_last_error) */
     LBM_ENONFINITE = 4,    /* a non-finite density was found */
     LBM_EUNSUPPORTED = 5   /* a parameter combination this build does not implement */

@@ -110,8 +110,8 @@ void launch_ref(lbm_domain* d, const lbm::StepArgs<Real>& a, hipStream_t s) {
     hipLaunchKernelGGL((lbm::k_collide<Real, FORCE, TY>), grid, dim3(lbm::NT), 0, s, a);
 }
 
-// Rows per marching block (default 8: the longest block that keeps two
-// workgroups per CU in LDS and registers, for both population precisions).
+// Rows per marching block (default 8: the fastest measured for both population
+// precisions; two workgroups per CU with FP64 populations, three with FP32).
 int march_rows(const lbm_domain* d) { return d->tile_y ? d->tile_y : 8; }
 
 // The marching kernel needs the geometric form along y (HDM, ny > 2R + 1) and
@@ -132,10 +132,17 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
     }
     int& per_cu = ty == 4 ? d->march_occ[0] : d->march_occ[1];  // cached occupancy query
     if (per_cu == 0) {
+        // the instantiation launch_march_t picks for this N_x (paired accesses when even)
+        const bool vec = d->p.nx % 2 == 0;
+        const auto occ = [&](const void* kern) {
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, lbm::NT, 0);
+        };
         if (ty == 4)
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 4, true>, lbm::NT, 0));
+            HIP_TRY(vec ? occ((const void*)lbm::k_march<Real, FORCE, 4, true>)
+                        : occ((const void*)lbm::k_march<Real, FORCE, 4, false>));
         else
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lbm::k_march<Real, FORCE, 8, true>, lbm::NT, 0));
+            HIP_TRY(vec ? occ((const void*)lbm::k_march<Real, FORCE, 8, true>)
+                        : occ((const void*)lbm::k_march<Real, FORCE, 8, false>));
         if (per_cu < 1) per_cu = 1;
     }
     const long target = (long)d->ncu * per_cu;
@@ -276,7 +283,7 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
     if (ncu < 1) ncu = 1;
 
     lbm_domain* d = new (std::nothrow) lbm_domain;
-    if (!d) return fail(LBM_EINVAL, "out of host memory");
+    if (!d) return fail(LBM_ENOMEM, "out of host memory");
     std::memset(d, 0, sizeof(*d));
     d->p = *p;
     d->Tc = Tc;

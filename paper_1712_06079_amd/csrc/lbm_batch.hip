@@ -197,7 +197,7 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace
     if (st != LBM_OK) return st;
     if (workspace_bytes < L.total) return fail(LBM_ENOMEM, "batch workspace %zu < %zu bytes", workspace_bytes, L.total);
     lbm_batch* b = new (std::nothrow) lbm_batch();
-    if (!b) return fail(LBM_EINVAL, "out of host memory");
+    if (!b) return fail(LBM_ENOMEM, "out of host memory");
     b->n = n;
     b->prec = params[0].prec;
     b->force = params[0].force;
