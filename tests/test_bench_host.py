@@ -1,0 +1,84 @@
+"""Host-side behaviour of bench.py (no GPU): the one-GPU contract and the
+bookkeeping that turns committed rocprofv3 summaries into the JSON fields."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _run_bench(args, env_extra=None):
+    env = dict(os.environ)
+    env.update(env_extra or {})
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,
+                          env=env, timeout=120)
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = _run_bench(["--gpus", str(n)])
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_world_size_above_one_is_refused():
+    r = _run_bench([], {"WORLD_SIZE": "2"})
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def _fake_profile(tmp_path, monkeypatch, kernel_hash):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"kernel_hash": kernel_hash, "hbm_bytes_per_launch": 3_000_000_000,
+           "hbm_read_bytes": 1_800_000_000, "hbm_write_bytes": 1_200_000_000}
+    (prof / "k_march_c5_f64_pmc.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+
+def test_stream_model_arithmetic(tmp_path, monkeypatch):
+    h = bench.kernel_hash()  # hash of the real kernel sources (read before ROOT moves)
+    _fake_profile(tmp_path, monkeypatch, h)
+    monkeypatch.setattr(bench, "kernel_hash", lambda: h)
+    probe = {"read": {"GBps": 6000.0}, "write": {"GBps": 4000.0}}
+    m = bench.stream_model("k_march", "c5", "f64", probe, launch_ms=0.75)
+    # 1.8 GB at 6 TB/s + 1.2 GB at 4 TB/s = 0.3 ms + 0.3 ms
+    assert m["model_ms"] == pytest.approx(0.6)
+    assert m["frac_of_model"] == pytest.approx(0.8)
+    assert m["read_bytes"] == 1_800_000_000 and m["write_bytes"] == 1_200_000_000
+    assert bench.traffic_from_profile("k_march", "c5", "f64") == 3_000_000_000
+
+
+def test_stale_profile_is_ignored(tmp_path, monkeypatch):
+    _fake_profile(tmp_path, monkeypatch, "0000000000000000")
+    monkeypatch.setattr(bench, "kernel_hash", lambda: "ffffffffffffffff")
+    probe = {"read": {"GBps": 6000.0}, "write": {"GBps": 4000.0}}
+    assert bench.stream_model("k_march", "c5", "f64", probe, launch_ms=0.75) is None
+    assert bench.traffic_from_profile("k_march", "c5", "f64") is None
+
+
+def test_stream_model_needs_both_probes(tmp_path, monkeypatch):
+    h = "abcdabcdabcdabcd"
+    _fake_profile(tmp_path, monkeypatch, h)
+    monkeypatch.setattr(bench, "kernel_hash", lambda: h)
+    assert bench.stream_model("k_march", "c5", "f64", {"read": {"GBps": 6000.0}}, 0.75) is None
+    assert bench.stream_model("k_march", "c5", "f64", None, 0.75) is None
+
+
+def test_kernel_hash_covers_the_kernel_sources():
+    """The hash that gates the profile-derived fields changes with any of the
+    kernel headers (here: with their concatenated bytes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for s in bench.KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1712_06079_amd", "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    assert bench.kernel_hash() == h.hexdigest()[:16]
+    assert "lbm_march.hpp" in bench.KERNEL_SOURCES and "lbm_device.hpp" in bench.KERNEL_SOURCES
