@@ -41,7 +41,8 @@
 //  3  collision of the interior and ring cells into the post-collision ring
 //     (rows yb-2 .. yb+TY-1);
 //  4  commit the loads of step 1 (LDS, block sums), issue the next block's
-//     interior populations (in flight through the next block's step 2),
+//     interior populations (in flight through the next block's step 2; with
+//     FP64 populations and TY = 8 they are issued at the start of step 3),
 //     then pull streaming of rows yb-1 .. yb+TY-2 (stored when inside
 //     [ys, ye)) and rho -> U -> phi_{t+1}.
 #pragma once
@@ -77,6 +78,12 @@ struct MarchShape {
     // VGPRs): three, two for the hybrid force (two potential fields).  The LDS
     // footprint may allow fewer (FP64 with TY = 8: two workgroups per CU).
     static constexpr int WAVES = FORCE == FORCE_HYBRID ? 2 : 3;
+    // Where the LDS already limits residency to two workgroups per CU (FP64,
+    // TY = 8) the spare registers hold the next block's populations one phase
+    // longer: they are loaded at the start of the collision phase instead of
+    // after the commit (with FP32 populations the extra registers cost more
+    // than the longer flight gains).
+    static constexpr bool EARLY_F = sizeof(Real) == 8 && TY == 8;
     static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
     static_assert((BAR_D + F_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
@@ -98,6 +105,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     using V2 = Real __attribute__((ext_vector_type(2)));
     constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, BR = M::BR, SEG = M::SEG;
     constexpr bool HYB = FORCE == FORCE_HYBRID;
+    constexpr bool EARLY_F = M::EARLY_F;
     __shared__ __align__(16) double sm[M::DOUBLES];
     __shared__ double ctab[TAB];               // sign-folded x coefficients (staged in the prologue)
     double* bar = sm;                          // [BR][RW] phi rows, x0-1-R .. x0+64+R; row y in slot bslot(y)
@@ -527,18 +535,24 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
 
         // Phase 3: collision of the interior cells, two per lane, and of the
         // ring cells.
+        double gc[M::NP][2][Q];
+#pragma unroll
+        for (int i = 0; i < M::NP; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) gc[i][h][q] = (double)fc[i][h][q];
+        if (EARLY_F) issue_f(yb + TY);  // the next block's populations, in flight from here on
 #pragma unroll
         for (int i = 0; i < M::NP; ++i) {
             const int t = tid + i * NT;
             if (t < M::NPAIR) {
                 const int r = t >> 5, lx0 = 2 * (t & 31);
                 const int ps = pslot(yb + r);
-                double g[2][Q];
+                double (&g)[2][Q] = gc[i];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int c = r * BX + lx0 + h;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) g[h][q] = (double)fc[i][h][q];
                     double rho, jx, jy;
                     moments(g[h], rho, jx, jy);
                     collide(g[h], rho, jx, jy, Fx[c], Fy[c], a.omega);
@@ -572,7 +586,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
         commit(yb + TY);
         commit_col();
         __builtin_amdgcn_sched_barrier(0);  // the commit's waits stay ahead of the new loads and stores
-        issue_f(yb + TY);
+        if (!EARLY_F) issue_f(yb + TY);
 
         // Pull streaming of rows yb-1 .. yb+TY-2 and phi_{t+1}.
 #pragma unroll
