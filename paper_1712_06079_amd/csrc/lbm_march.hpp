@@ -68,11 +68,8 @@ struct MarchShape {
     static constexpr int F_D = 2 * TY * BX + 2 * NRING;     // F_x, F_y of the interior and of the ring cells
     static constexpr int FRING_D = (NRING * Q * (int)sizeof(Real) + 7) / 8;
     static constexpr int POST_D = (Q * PR * CWP * (int)sizeof(Real) + 7) / 8;
-    static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue staging
-    static constexpr int SCR_D = POST_D > WARM_ROWS * CW ? (POST_D > WSUM_ROWS * CW ? POST_D : WSUM_ROWS * CW)
-                                                         : (WARM_ROWS * CW > WSUM_ROWS * CW ? WARM_ROWS * CW
-                                                                                           : WSUM_ROWS * CW);
-    static constexpr int DOUBLES = BAR_D + F_D + FRING_D + SCR_D;
+    static constexpr int WARM_ROWS = R - 3, WSUM_ROWS = NB * TY + 1;  // prologue rows per column
+    static constexpr int DOUBLES = BAR_D + F_D + FRING_D + POST_D;
     static constexpr int XBASE = 2 * BX;                    // first x lane
     // Waves per SIMD the register allocation must allow (at most 512 / WAVES
     // VGPRs): three, two for the hybrid force (two potential fields).  The LDS
@@ -114,8 +111,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     double* FxR = Fy + TY * BX;                // [2TY] x force of the ring cells
     double* FyR = FxR + M::NRING;              // [2TY] y force of the ring cells
     Real* fring = reinterpret_cast<Real*>(FyR + M::NRING);                  // [2TY][Q] ring-cell f
-    double* scr = FyR + M::NRING + M::FRING_D;                              // prologue staging
-    Real* post = reinterpret_cast<Real*>(scr);                              // [Q][PR][CWP]
+    Real* post = reinterpret_cast<Real*>(FyR + M::NRING + M::FRING_D);      // [Q][PR][CWP]
 
     // Lane-dependent indices are re-derived in every block from a copy of the
     // thread index that the compiler cannot treat as loop-invariant: hoisting
@@ -313,75 +309,56 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     };
 
     // ------------------------------------------------------------- prologue
-    // Forward y state up to the first block (updates at rows yb0-(R-3) ..
-    // yb0-2 read rows yb0-R .. yb0-4), the block sums W_1 .. W_NB of block 0
-    // (rows yb0+3+TY .. yb0+3+(NB+1)TY), staged in the post-collision area, and
-    // the bar rows yb0-4 .. yb0+TY+3.
-    auto stage_rows = [&](int ylo, int nrows) {
-        const int n = nrows * CW;
-        for (int i0 = 0; i0 < n; i0 += 8 * NT) {
-            double v[8];
+    // The bar rows yb0-4 .. yb0+TY+3 go to LDS; each column lane reads its own
+    // column's rows straight into registers for the forward y state up to the
+    // first block (updates at rows yb0-(R-3) .. yb0-2 read rows yb0-R ..
+    // yb0-4) and for the block sums W_1 .. W_NB of block 0 (rows yb0+3+TY ..
+    // yb0+3+(NB+1)TY).  The bar and warm-up loads are issued together, the
+    // block-sum rows next: two memory round trips and one barrier before the
+    // march.
+    constexpr int BP = (M::BAR_D + NT - 1) / NT;
+    double vb[BP];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = min(i0 + tid + j * NT, n - 1);
-                const int r = i / CW, c = i - r * CW;
-                v[j] = a.phi_in[(long)wrapy(ylo + r) * pitch + wrap(x0 - 1 + c, nx)];
-            }
+    for (int j = 0; j < BP; ++j) {
+        const int i = min(tid + j * NT, M::BAR_D - 1);  // past the end: a duplicate, not stored
+        const int r = i / RW, c = i - r * RW;
+        vb[j] = a.phi_in[(long)wrapy(yb0 - 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
+    }
+    const double* colp = a.phi_in + xcol;  // this lane's column (waves 0-1)
+    double u[M::WARM_ROWS];
+    if (colw) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = i0 + tid + j * NT;
-                if (i < n) scr[i] = v[j];
-            }
+        for (int m = 0; m < M::WARM_ROWS; ++m) u[m] = colp[(long)wrapy(yb0 - R + m) * pitch];
+    }
+#pragma unroll
+    for (int j = 0; j < BP; ++j) {
+        const int i = tid + j * NT;
+        if (i < M::BAR_D) {
+            const int r = i / RW, c = i - r * RW;
+            bar[bslot(yb0 - 4 + r) * RW + c] = vb[j];
         }
-    };
-    stage_rows(yb0 - R, M::WARM_ROWS);
+    }
     for (int i = tid; i < TAB; i += NT) ctab[i] = a.tab->tx_tab[i];
-    {
-        const int n = M::BAR_D;
-        for (int i0 = 0; i0 < n; i0 += 8 * NT) {
-            double v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = min(i0 + tid + j * NT, n - 1);
-                const int r = i / RW, c = i - r * RW;
-                v[j] = a.phi_in[(long)wrapy(yb0 - 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = i0 + tid + j * NT;
-                if (i < n) {
-                    const int r = i / RW, c = i - r * RW;
-                    bar[bslot(yb0 - 4 + r) * RW + c] = v[j];
-                }
-            }
-        }
-    }
-    __syncthreads();
     if (colw) {
+#pragma unroll
         for (int m = 1; m <= R - 4; ++m) {
-            const double v2 = scr[m * CW + ccol], v3 = scr[(m - 1) * CW + ccol];
-            l = fma(rr, l, rr4 * (op(v2) - op(v3)));
-            if (HYB) lu = fma(rr, lu, rr4 * (opu(v2) - opu(v3)));
+            l = fma(rr, l, rr4 * (op(u[m]) - op(u[m - 1])));
+            if (HYB) lu = fma(rr, lu, rr4 * (opu(u[m]) - opu(u[m - 1])));
         }
-    }
-    __syncthreads();
-    stage_rows(yb0 + 3 + TY, M::WSUM_ROWS);
-    __syncthreads();
-    if (colw) {
+        double w[M::WSUM_ROWS];
+#pragma unroll
+        for (int i = 0; i < M::WSUM_ROWS; ++i) w[i] = colp[(long)wrapy(yb0 + 3 + TY + i) * pitch];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            double p[TY];
+            double pj[TY];
 #pragma unroll
-            for (int n = 0; n < TY; ++n) p[n] = scr[(j * TY + n + 1) * CW + ccol];
-            const double s0 = scr[j * TY * CW + ccol];
-            W[j] = block_sum(op(s0), p, false);
-            if (HYB) Wu[j] = block_sum(opu(s0), p, true);
+            for (int n = 0; n < TY; ++n) pj[n] = w[j * TY + n + 1];
+            W[j] = block_sum(op(w[j * TY]), pj, false);
+            if (HYB) Wu[j] = block_sum(opu(w[j * TY]), pj, true);
         }
-        const double last = scr[NB * TY * CW + ccol];
-        uprev = op(last);
-        uprevu = opu(last);
+        uprev = op(w[NB * TY]);
+        uprevu = opu(w[NB * TY]);
     }
-    __syncthreads();
     issue_fr(yb0);
     issue_f(yb0);
     if (tid < M::NRING * Q) fring[tid] = (Real)fr;
