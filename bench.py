@@ -480,13 +480,13 @@ def main():
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
     if args.gpus > 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: launched with WORLD_SIZE > 1; this build runs on one GPU", file=sys.stderr)
+        print("bench.py: launched with WORLD_SIZE > 1; the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile, args.chunks)

@@ -50,7 +50,7 @@ typedef enum {
     LBM_ENOMEM = 2,        /* workspace smaller than lbm_workspace_bytes(), or host memory exhausted */
     LBM_EDEVICE = 3,       /* a HIP call failed (message in lbm_last_error) */
     LBM_ENONFINITE = 4,    /* a non-finite density was found */
-    LBM_EUNSUPPORTED = 5   /* a parameter combination this build does not implement */
+    LBM_EUNSUPPORTED = 5   /* a parameter combination the library does not implement */
 } lbm_status;
 
 typedef enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_CS = 2, LBM_EOS_RK = 3, LBM_EOS_RKS = 4 } lbm_eos;
