@@ -162,6 +162,20 @@ def test_march_forces(eos, force):
         assert rel_err(got["rho"], ref["rho"]) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
+def test_march_forces_eight_row_blocks(force, prec):
+    """Every force on the marching kernel with 8-row blocks (the default; with
+    FP64 populations the next block's populations are loaded one phase
+    earlier), both population precisions, short and long x axes."""
+    for nx, ny in ((40, 100), (140, 88)):
+        po, rho0, ux0, uy0 = variant_case("pr", force, nx, ny, seed=3 * nx + ny)
+        ref = oracle_run(po, rho0, 30, ux0, uy0)
+        got = gpu_run(po, rho0, 30, prec, ux0, uy0, variant=3, tile=8, chunks=2)
+        assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+        assert np.max(np.abs(got["f"] - ref["f"])) < TOL[prec] * np.max(np.abs(ref["f"]))
+
+
 def test_march_rejects_short_y():
     po, rho0, _, _ = variant_case("vdw", "sc", 96, 64, seed=1)
     d = L.Domain(lib_params(po), dev(rho0))
