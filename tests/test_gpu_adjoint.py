@@ -183,3 +183,81 @@ def test_adjoint_steps_equal_single_steps(force):
     torch.cuda.synchronize()
     assert torch.equal(lam_a, lam_b)
     assert torch.allclose(grad_a, grad_b, rtol=1e-12, atol=0.0), (grad_a, grad_b)
+
+
+
+def _c4_case():
+    """The differentiation workload: 256 x 256 Carnahan-Starling droplet
+    (R = 48, W = 4) at T = 0.7 Tc, tau = 1, SC + HDM."""
+    po = PINS.eos_params("cs")
+    po.nx = po.ny = 256
+    po.force, po.tau = "sc", 1.0
+    tc, _ = O.critical(po)
+    po.T = 0.7 * tc
+    rv, rl, _ = O.maxwell(po, po.T)
+    return po, I.droplet(256, 256, rv, rl, 48.0, 4.0)
+
+
+def _c4_target(po, rho0, n):
+    """Oracle densities after n steps of the same setup at g = 1.02."""
+    pt = PINS.eos_params("cs")
+    pt.nx, pt.ny, pt.force, pt.tau, pt.T, pt.g = po.nx, po.ny, po.force, po.tau, po.T, 1.02
+    return O.moments(pt, O.run(pt, O.init(pt, rho0), n))["rho"]
+
+
+def test_full_size_gradient_finite_differences():
+    """The differentiation workload at full size (5000 steps, a snapshot every
+    70, the configuration the benchmark times), J = sum (rho_5000 -
+    rho_target)^2: autograd gradients against central differences of GPU
+    rollouts for g, T and three seeded directions of rho0 (every step 1e-6
+    relative: a direction is a seeded normal field times rho0)."""
+    po, rho0 = _c4_case()
+    n, every = 5000, 70
+    tgt = dev(_c4_target(po, rho0, n))
+    p = lib_params(po)
+    r0 = dev(rho0).requires_grad_(True)
+    g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(po.T, dtype=torch.float64, requires_grad=True)
+    Jv = ((rollout(r0, g, T, p, n, every=every) - tgt) ** 2).sum()
+    Jv.backward()
+    dr = r0.grad.cpu().numpy()
+
+    def J(r, gv, Tv):
+        with torch.no_grad():
+            return float(((rollout(dev(r), torch.tensor(gv, dtype=torch.float64), torch.tensor(Tv, dtype=torch.float64),
+                                   p, n) - tgt) ** 2).sum())
+
+    assert abs(J(rho0, 1.0, po.T) / Jv.item() - 1) < 1e-13
+    hg, hT = 1e-6, 1e-6 * po.T
+    fd_g = (J(rho0, 1 + hg, po.T) - J(rho0, 1 - hg, po.T)) / (2 * hg)
+    fd_T = (J(rho0, 1.0, po.T + hT) - J(rho0, 1.0, po.T - hT)) / (2 * hT)
+    assert abs(g.grad.item() / fd_g - 1) < 1e-5, (g.grad.item(), fd_g)
+    assert abs(T.grad.item() / fd_T - 1) < 1e-5, (T.grad.item(), fd_T)
+    for s in range(3):
+        dirn = I.gaussian(rho0.shape, 1.0, seed=100 + s) * rho0
+        hr = 1e-6
+        fd_r = (J(rho0 + hr * dirn, 1.0, po.T) - J(rho0 - hr * dirn, 1.0, po.T)) / (2 * hr)
+        ad_r = float((dr * dirn).sum())
+        assert abs(ad_r / fd_r - 1) < 1e-5, (s, ad_r, fd_r)
+
+
+def test_full_field_gradient_matches_oracle_at_full_lattice():
+    """The full 256 x 256 lattice of the differentiation workload over 350
+    steps (five checkpoint segments of 70): every component of dJ/drho0 and
+    dJ/dg, dJ/dT against the oracle's checkpointed adjoint (the oracle's
+    reverse sweep over the whole 5000 steps would take minutes)."""
+    po, rho0 = _c4_case()
+    n, every = 350, 70
+    target = _c4_target(po, rho0, n)
+    ref = O.adjoint_run(po, rho0, target, n, every=every)
+    p = lib_params(po)
+    r0 = dev(rho0).requires_grad_(True)
+    g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(po.T, dtype=torch.float64, requires_grad=True)
+    Jv = ((rollout(r0, g, T, p, n, every=every) - dev(target)) ** 2).sum()
+    Jv.backward()
+    assert abs(Jv.item() / ref["J"] - 1) < 1e-10
+    dr = r0.grad.cpu().numpy()
+    assert np.max(np.abs(dr - ref["drho0"])) < 1e-9 * np.abs(ref["drho0"]).max()
+    assert abs(g.grad.item() / ref["dg"] - 1) < 1e-9, (g.grad.item(), ref["dg"])
+    assert abs(T.grad.item() / ref["dT"] - 1) < 1e-9, (T.grad.item(), ref["dT"])
