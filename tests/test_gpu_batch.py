@@ -122,3 +122,39 @@ def test_per_domain_nonfinite_flags():
     f[2, 1, 5] = float("nan")
     d.set_populations(f)
     assert b.check_finite() == [i == 3 for i in range(8)]
+
+
+def test_full_coexistence_sweep():
+    """The full sweep the benchmark times: 64 domains (N_x in {128, 256, 512},
+    N_y in {8, 16, 32} from seed 2024; 32 Peng-Robinson with a = 2/49, then 32
+    Carnahan-Starling; T_r = linspace(0.5, 0.95, 32) per group), under the
+    schedule the autotuner picks.  After 50 batched steps every domain is
+    bitwise the single-domain kernel's result, and eight domains spread over
+    both groups and all shapes match the oracle."""
+    seed = 2024
+    nxs, nys = I.batch_shapes(64, seed)
+    trs = np.linspace(0.5, 0.95, 32)
+    ps, rhos = [], []
+    for i in range(64):
+        pr = i < 32
+        p = L.Params(nx=nxs[i], ny=nys[i], eos="pr" if pr else "cs", force="sc", a=2 / 49 if pr else 1.0,
+                     b=2 / 21 if pr else 4.0, R=1.0, omega=0.344, k=0.04, tau=1.0)
+        tc, _ = L.critical(p)
+        p.T = trs[i % 32] * tc
+        rv, rl, _ = L.maxwell(p, p.T)
+        ps.append(p)
+        rhos.append(I.slab(p.nx, p.ny, rv, rl, 5.0, axis="x", noise=1e-4 * rv, seed=seed + i))
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    b.autotune(probe_steps=10)
+    n = 50
+    b.step(n)
+    assert not any(b.check_finite())  # per-domain non-finite flags
+    for i, (p, r) in enumerate(zip(ps, rhos)):
+        d = L.Domain(p, dev(r))
+        d.step(n)
+        assert np.array_equal(b.domain(i).populations().cpu().numpy(), d.populations().cpu().numpy()), i
+    for i in (0, 9, 17, 31, 32, 45, 50, 63):
+        po = to_oracle(ps[i])
+        ref = O.moments(po, O.run(po, O.init(po, rhos[i]), n))["rho"]
+        got = b.domain(i).moments()["rho"].cpu().numpy()
+        assert np.max(np.abs(got - ref) / ref) < 1e-12, i
