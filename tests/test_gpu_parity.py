@@ -290,3 +290,21 @@ def test_full_size_large_dynamic_case(prec):
     ref = oracle_run(po, rho0, 3, ux0, uy0)
     assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
     assert abs(got["totals"][0] / ref["rho"].sum() - 1) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_single_droplet(prec):
+    """The 1024^2 Carnahan-Starling droplet at T = 0.6 Tc (R = 128, W = 4),
+    Zhang-Chen + HDM, tau = 1, in the launch configuration the benchmark
+    times (automatic kernel choice): 20 GPU steps against 20 oracle steps at
+    full size."""
+    po = PINS.eos_params("cs")
+    tc, _ = O.critical(po)
+    po.nx = po.ny = 1024
+    po.force, po.tau, po.T = "zc", 1.0, 0.6 * tc
+    rv, rl, _ = O.maxwell(po, po.T)
+    rho0 = I.droplet(1024, 1024, rv, rl, 128.0, 4.0)
+    got = gpu_run(po, rho0, 20, prec)
+    ref = oracle_run(po, rho0, 20)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+    assert abs(got["totals"][0] / ref["rho"].sum() - 1) < TOL[prec]
