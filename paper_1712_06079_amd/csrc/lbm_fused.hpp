@@ -30,7 +30,8 @@ struct FusedShape {
     static constexpr int NCELL = CW * CH;
     static constexpr int NSX = (CW + K - 1) / K;              // x segments per collision row (explicit form)
     static constexpr int NSY = (CH + K - 1) / K;              // y segments per collision column (explicit form)
-    static constexpr int NSEGX = 4;                           // x segments per collision row (recursive form)
+    static constexpr int NSEGX = 8;                           // x segments per collision row (recursive form; 8 keeps each
+                                                              // item's chain short and a 4-row tile's items in one pass)
     static constexpr int SX = (CW + NSEGX - 1) / NSEGX;       // outputs per recursive x segment
     static constexpr int XSPAN = NSX * K > NSEGX * SX ? NSX * K : NSEGX * SX;
     static constexpr int RW = (XSPAN + 2 * RX) | 1;           // row-bar pitch (odd: spreads LDS banks)
