@@ -18,9 +18,17 @@ import torch
 from . import Domain, Params
 
 
+def _check_schedule(nsteps: int, every: int):
+    if int(nsteps) != nsteps or nsteps < 0:
+        raise ValueError(f"nsteps must be a non-negative integer (got {nsteps})")
+    if int(every) != every or every < 1:
+        raise ValueError(f"every (steps between snapshots) must be a positive integer (got {every})")
+
+
 class HDMRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho0, g, T, params: Params, nsteps: int, every: int = 70):
+        _check_schedule(nsteps, every)
         p = dataclasses.replace(params, g=float(g), T=float(T), prec="f64")
         d = Domain(p, rho0.detach().contiguous())
         nseg = max(1, math.ceil(nsteps / every))

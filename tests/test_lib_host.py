@@ -99,3 +99,12 @@ def test_workspace_size_formula():
         assert lib.lbm_workspace_bytes(C.byref(p.c()), C.byref(nb)) == 0
         pitch = 128
         assert nb.value >= 2 * 9 * pitch * 37 * es + 2 * pitch * 37 * es
+
+
+@pytest.mark.parametrize("nsteps,every", [(-1, 70), (10, 0), (10, -3), (2.5, 70), (10, 1.5)])
+def test_rollout_rejects_bad_schedule(nsteps, every):
+    """The differentiable rollout validates its checkpoint schedule before it
+    touches the device."""
+    from paper_1712_06079_amd.autograd import _check_schedule
+    with pytest.raises(ValueError):
+        _check_schedule(nsteps, every)
