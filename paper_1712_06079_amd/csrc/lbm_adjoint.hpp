@@ -63,7 +63,7 @@ __device__ inline void eos_parts(int kind, double b, double rho, double& rep, do
     }
 }
 
-__device__ inline void dA(int i, double rho, double ir, double mx, double my, double& dr, double& dmx, double& dmy) {
+__device__ inline void dA(int i, double ir, double mx, double my, double& dr, double& dmx, double& dmy) {
     const double em = double(ex(i)) * mx + double(ey(i)) * my;
     const double m2 = mx * mx + my * my;
     const double w = wq<double>(i);
@@ -130,8 +130,8 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
             ys = ys < 0 ? a.ny - 1 : (ys >= a.ny ? 0 : ys);
             mu[i] = A.lam_next[i * n + (long)ys * a.nx + xs];
             double ar, axx, ayy, br, bx, by;
-            dA(i, rho, ir, jx, jy, ar, axx, ayy);
-            dA(i, rho, ir, mx, my, br, bx, by);
+            dA(i, ir, jx, jy, ar, axx, ayy);
+            dA(i, ir, mx, my, br, bx, by);
             rb += mu[i] * ((w - 1.0) * ar + br);
             jbx += mu[i] * ((w - 1.0) * axx + bx);
             jby += mu[i] * ((w - 1.0) * ayy + by);
@@ -251,7 +251,7 @@ static __global__ void __launch_bounds__(NT) k_adj_accumulate(const double* __re
 }
 
 // dJ/drho0 = sum_i lam0_i f^eq_i(rho0, u0) / rho0 (f^eq is linear in rho at fixed u).
-static __global__ void __launch_bounds__(NT) k_adj_rho0(const double* __restrict__ lam0, const double* __restrict__ rho0,
+static __global__ void __launch_bounds__(NT) k_adj_rho0(const double* __restrict__ lam0,
                                                  const double* __restrict__ ux0, const double* __restrict__ uy0,
                                                  long n, double* __restrict__ out) {
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {

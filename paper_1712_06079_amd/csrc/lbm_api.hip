@@ -645,7 +645,7 @@ lbm_status lbm_adjoint_rho0(lbm_domain* d, const double* lam0, const double* ux0
                             hipStream_t stream) {
     if (!d || !lam0 || !drho0) return fail(LBM_EINVAL, "NULL argument");
     const long n = (long)d->p.nx * d->p.ny;
-    hipLaunchKernelGGL(lbm::k_adj_rho0, dim3(grid_1d(n)), dim3(lbm::NT), 0, stream, lam0, (const double*)nullptr, ux0, uy0,
+    hipLaunchKernelGGL(lbm::k_adj_rho0, dim3(grid_1d(n)), dim3(lbm::NT), 0, stream, lam0, ux0, uy0,
                        n, drho0);
     HIP_TRY(hipGetLastError());
     return LBM_OK;

@@ -38,8 +38,13 @@ struct lbm_batch {
 
 namespace {
 
+// Fill n ints with v (clears the per-domain flags on the stream, also where a
+// memset node would not be wanted).
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
 constexpr int GRAPH_STEPS = 16;  // launches per captured graph (even: parity is restored)
-constexpr int MAX_TILES_PER_DOMAIN_ROWS = 8;
 
 size_t desc_size(int prec) { return prec == LBM_F32 ? sizeof(lbm::StepArgs<float>) : sizeof(lbm::StepArgs<double>); }
 
@@ -125,7 +130,7 @@ lbm_status upload_tiles(lbm_batch* b, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(b->ws + b->off_tiles, t.data(), t.size() * sizeof(lbm::BatchTile), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (b->graph_ok) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->graph_ok = false;
     }
     return LBM_OK;
@@ -139,7 +144,7 @@ lbm_status ensure_graph(lbm_batch* b) {
     hipError_t e = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
     b->graph_ok = true;
     return LBM_OK;
@@ -380,8 +385,8 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
                 rep += buf;
                 if (ms < best) { best = ms; bt = ty; bo = order; bg = grid; }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     char buf[128];
     snprintf(buf, sizeof(buf), ", \"best\": \"ty%d_o%d_g%d\"}", bt, bo, bg);
     rep += buf;
@@ -408,7 +413,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
 lbm_status lbm_batch_check_finite(lbm_batch* b, int32_t* flags, hipStream_t stream) {
     if (!b || !flags) return fail(LBM_EINVAL, "NULL argument");
     int* df = reinterpret_cast<int*>(b->ws + b->off_flags);
-    hipLaunchKernelGGL(lbm::k_fill_int, dim3(1), dim3(lbm::NT), 0, stream, df, b->n, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(lbm::NT), 0, stream, df, b->n, 0);
     const int ty = b->tile_y;
     if (b->prec == LBM_F32) {
         const auto* descs = reinterpret_cast<const lbm::StepArgs<float>*>(b->ws + b->off_desc[b->cur]);
@@ -430,8 +435,8 @@ lbm_status lbm_batch_check_finite(lbm_batch* b, int32_t* flags, hipStream_t stre
 
 void lbm_batch_destroy(lbm_batch* b) {
     if (!b) return;
-    if (b->graph_ok) hipGraphExecDestroy(b->exec);
-    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->graph_ok) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     for (auto* d : b->doms) lbm_destroy(d);
     delete b;
 }

@@ -353,10 +353,6 @@ __global__ void __launch_bounds__(NT) k_batch_finite(const StepArgs<Real>* __res
     }
 }
 
-static __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
-}
-
 template <typename Real, int FORCE, int TX, int TY, int K>
 inline void launch_fused_t(const StepArgs<Real>& a, hipStream_t s) {
     dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);

@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
 
 // One workgroup: thread t sums partials t, t + 256, ... in order, then a fixed
 // butterfly and the four wavefronts in index order.
-static __global__ void __launch_bounds__(NT) k_totals(const double* __restrict__ partial, long nblocks, double* __restrict__ out) {
+static __global__ void __launch_bounds__(NT) __attribute__((unused)) k_totals(const double* __restrict__ partial, long nblocks, double* __restrict__ out) {
     __shared__ double red[4][NT / BX];
     double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     for (long b = threadIdx.x; b < nblocks; b += NT) {
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_set_f(StepArgs<Real> a, const double* __
 
 // Validation of an initial density: flag[0] = 1 if any rho0 is non-finite,
 // <= 0 or at / beyond the pole of the repulsive term.
-static __global__ void __launch_bounds__(NT) k_check_rho0(const double* __restrict__ rho0, long n, double rho_max,
+static __global__ void __launch_bounds__(NT) __attribute__((unused)) k_check_rho0(const double* __restrict__ rho0, long n, double rho_max,
                                                    int* __restrict__ flag) {
     int bad = 0;
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
