@@ -261,3 +261,33 @@ def test_full_field_gradient_matches_oracle_at_full_lattice():
     assert np.max(np.abs(dr - ref["drho0"])) < 1e-9 * np.abs(ref["drho0"]).max()
     assert abs(g.grad.item() / ref["dg"] - 1) < 1e-9, (g.grad.item(), ref["dg"])
     assert abs(T.grad.item() / ref["dT"] - 1) < 1e-9, (T.grad.item(), ref["dT"])
+
+
+def test_zero_steps_are_identities():
+    """Empty inputs: zero steps leave the populations as they are, zero
+    reverse steps leave the cotangent and the parameter gradients untouched,
+    and a zero-step rollout is the identity (dJ/drho0 = 2 (rho0 - target),
+    nothing flows to g or T)."""
+    po, rho0, _, _ = case("cs", "sc", 70, 96)
+    d = L.Domain(lib_params(po), dev(rho0))
+    f0 = d.populations().clone()
+    d.step(0)
+    assert torch.equal(d.populations(), f0)
+    seg = d.new_states(2)
+    d.record(seg, 0)
+    lam = torch.randn((9, po.ny, po.nx), dtype=torch.float64, device="cuda")
+    lam_keep = lam.clone()
+    lam2 = torch.empty_like(lam)
+    grad = torch.tensor([0.25, -0.5], dtype=torch.float64, device="cuda")
+    d.adjoint_steps(seg, 0, lam, lam2, grad, d.adjoint_workspace())
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam_keep) and grad.tolist() == [0.25, -0.5]
+    target = dev(rho0 * 1.01)
+    r0 = dev(rho0).requires_grad_(True)
+    g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(po.T, dtype=torch.float64, requires_grad=True)
+    rho = rollout(r0, g, T, lib_params(po), 0)
+    ((rho - target) ** 2).sum().backward()
+    assert torch.allclose(rho.detach(), dev(rho0), rtol=1e-15, atol=0)
+    assert torch.allclose(r0.grad, 2 * (dev(rho0) - target), rtol=1e-13, atol=1e-15)
+    assert g.grad.item() == 0.0 and T.grad.item() == 0.0
