@@ -42,9 +42,10 @@
 //     (rows yb-2 .. yb+TY-1);
 //  4  commit the loads of step 1 (LDS, block sums), issue the next block's
 //     interior populations (in flight through the next block's step 2; with
-//     FP64 populations and TY = 8 they are issued at the start of step 3),
-//     then pull streaming of rows yb-1 .. yb+TY-2 (stored when inside
-//     [ys, ye)) and rho -> U -> phi_{t+1}.
+//     FP64 populations and TY = 8 they are issued earlier: in step 1 with the
+//     potential rows, or for the hybrid force at the start of step 3), then
+//     pull streaming of rows yb-1 .. yb+TY-2 (stored when inside [ys, ye))
+//     and rho -> U -> phi_{t+1}.
 #pragma once
 
 #include "lbm_fused.hpp"
@@ -77,11 +78,16 @@ struct MarchShape {
     // workgroups per CU anyway.
     static constexpr int WAVES = (FORCE == FORCE_HYBRID || (sizeof(Real) == 8 && TY == 8)) ? 2 : 3;
     // Where the LDS already limits residency to two workgroups per CU (FP64,
-    // TY = 8) the spare registers hold the next block's populations one phase
-    // longer: they are loaded at the start of the collision phase instead of
-    // after the commit (with FP32 populations the extra registers cost more
-    // than the longer flight gains).
-    static constexpr bool EARLY_F = sizeof(Real) == 8 && TY == 8;
+    // TY = 8) the spare registers hold the next block's populations longer:
+    // they are loaded at the top of the block, with the potential rows, and
+    // stay in flight through the force and collision phases while the
+    // current block's copy is collided (TOP_F; 4096^2: +8 %).  The hybrid
+    // force's second potential field leaves no room for that: it loads them
+    // at the start of the collision phase (EARLY_F).  With FP32 populations
+    // the extra registers cost more than the longer flight gains (loading at
+    // the top: -6.5 %), so they load after the commit.
+    static constexpr bool TOP_F = sizeof(Real) == 8 && TY == 8 && FORCE != FORCE_HYBRID;
+    static constexpr bool EARLY_F = sizeof(Real) == 8 && TY == 8 && FORCE == FORCE_HYBRID;
     static_assert(NPAIR % 32 == 0 && NP >= 1, "block rows must fill whole half-wavefronts");
     static_assert((BAR_D + F_D + FRING_D) % 2 == 0, "post-collision rows must be 16-byte aligned");
     static_assert(NRING <= BX, "ring lanes must fit in one wavefront");
@@ -103,7 +109,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     using V2 = Real __attribute__((ext_vector_type(2)));
     constexpr int CW = M::CW, CWP = M::CWP, PR = M::PR, RW = M::RW, NB = M::NB, BR = M::BR, SEG = M::SEG;
     constexpr bool HYB = FORCE == FORCE_HYBRID;
-    constexpr bool EARLY_F = M::EARLY_F;
+    constexpr bool TOP_F = M::TOP_F, EARLY_F = M::EARLY_F;
     __shared__ __align__(16) double sm[M::DOUBLES];
     __shared__ double ctab[TAB];               // sign-folded x coefficients (staged in the prologue)
     double* bar = sm;                          // [BR][RW] phi rows, x0-1-R .. x0+64+R; row y in slot bslot(y)
@@ -177,7 +183,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     double pfar[TY];                  // loads of the rows NB blocks ahead (this lane's column)
     StageRegs<TY * RW> sbar;          // loads of the bar rows entering the ring
     double fr = 0.0;                  // one ring-cell population (tid < 2 TY Q)
-    Real fc[M::NP][2][Q];             // interior populations (loaded one phase 4 ahead)
+    Real fc[M::NP][2][Q];             // interior populations of the next block (in flight)
 
     // Loads of block yn (all unconditional; lanes with no use load a clamped
     // valid address) and their commit.
@@ -379,10 +385,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
         // are computing (FP32 populations +1.6 %, FP64 +0.4 %; keeping it
         // through the streaming stores where the populations load late: FP32
         // +0.5 % more).
+        // This block's interior populations: with TOP_F they are copied out
+        // here, and the next block's are issued after the potential rows.
+        double gc[M::NP][2][Q];
+        auto take_f = [&]() {
+#pragma unroll
+            for (int i = 0; i < M::NP; ++i)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) gc[i][h][q] = (double)fc[i][h][q];
+        };
+        if (TOP_F) take_f();
         __builtin_amdgcn_s_setprio(2);
         issue_col(yb + TY);
         issue_bar(yb + TY);
         issue_fr(yb + TY);
+        if (TOP_F) issue_f(yb + TY);
         __builtin_amdgcn_s_setprio(0);
 
         // Phase 2: forces of the interior and of the ring cells.
@@ -520,13 +539,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
 
         // Phase 3: collision of the interior cells, two per lane, and of the
         // ring cells.
-        double gc[M::NP][2][Q];
-#pragma unroll
-        for (int i = 0; i < M::NP; ++i)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) gc[i][h][q] = (double)fc[i][h][q];
+        if (!TOP_F) take_f();
         if (EARLY_F) {  // the next block's populations, in flight from here on
             __builtin_amdgcn_s_setprio(2);
             issue_f(yb + TY);
@@ -575,7 +588,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
         commit(yb + TY);
         commit_col();
         __builtin_amdgcn_sched_barrier(0);  // the commit's waits stay ahead of the new loads and stores
-        if (!EARLY_F) {  // (the raised priority is kept through this block's streaming stores)
+        if (!TOP_F && !EARLY_F) {  // (the raised priority is kept through this block's streaming stores)
             __builtin_amdgcn_s_setprio(2);
             issue_f(yb + TY);
         }
@@ -623,7 +636,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                 }
             }
         }
-        if (!EARLY_F) __builtin_amdgcn_s_setprio(0);
+        if (!TOP_F && !EARLY_F) __builtin_amdgcn_s_setprio(0);
 
         __syncthreads();
     }
