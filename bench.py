@@ -456,6 +456,50 @@ def cpu_baseline(name: str, sample_steps: int):
             "kind": "oracle", "sample": f"{sample_steps} FP64 steps of the {p.nx}x{p.ny} workload ({dt:.1f} s)"}
 
 
+def oracle_configs(c1_steps: int = 2000, c2_steps: int = 200, c4_steps: int = 140, every: int = 70):
+    """The FP64 oracle timed on the host cores for the other configurations
+    (a reported baseline, not a target): the 64^2 VDW slab in full, a sample
+    of the 1024^2 droplet, and a sample of the 256^2 differentiation workload
+    (forward steps, then the checkpointed forward + reverse of J)."""
+    import oracle as O
+    out = {"kind": "oracle", "cores": O.threads()}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t0
+
+    # 64 x 64 VDW slab, T = 0.9 Tc, SC + HDM
+    p = O.Params(nx=64, ny=64, eos="vdw", force="sc", grad="hdm", tau=1.0, a=9 / 49, b=2 / 21, R=1.0, k=0.01)
+    p.T = 0.9 * O.critical(p)[0]
+    rv, rl, _ = O.maxwell(p, p.T)
+    f = O.init(p, I.slab(64, 64, rv, rl, 5.0, axis="y", noise=1e-4, seed=1))
+    _, dt = timed(lambda: O.run(p, f, c1_steps))
+    out["c1"] = {"workload": "64x64 VDW T=0.9Tc SC+HDM slab", "steps": c1_steps, "s": round(dt, 3),
+                 "mlups": round(64 * 64 * c1_steps / dt / 1e6, 3)}
+    # 1024 x 1024 CS droplet, T = 0.6 Tc, ZC + HDM
+    p = O.Params(nx=1024, ny=1024, eos="cs", force="zc", grad="hdm", tau=1.0, a=1.0, b=4.0, R=1.0, k=0.04)
+    p.T = 0.6 * O.critical(p)[0]
+    rv, rl, _ = O.maxwell(p, p.T)
+    f = O.init(p, I.droplet(1024, 1024, rv, rl, 128.0, 4.0))
+    _, dt = timed(lambda: O.run(p, f, c2_steps))
+    out["c2"] = {"workload": "1024x1024 CS T=0.6Tc ZC+HDM droplet R=128", "steps": c2_steps, "s": round(dt, 3),
+                 "mlups": round(1024 * 1024 * c2_steps / dt / 1e6, 3)}
+    # 256 x 256 CS droplet, T = 0.7 Tc, SC + HDM: forward, then J and its gradients
+    p = O.Params(nx=256, ny=256, eos="cs", force="sc", grad="hdm", tau=1.0, a=1.0, b=4.0, R=1.0, k=0.04)
+    p.T = 0.7 * O.critical(p)[0]
+    rv, rl, _ = O.maxwell(p, p.T)
+    rho0 = I.droplet(256, 256, rv, rl, 48.0, 4.0)
+    f = O.init(p, rho0)
+    _, dt_f = timed(lambda: O.run(p, f, c4_steps))
+    _, dt_g = timed(lambda: O.adjoint_run(p, rho0, rho0, c4_steps, every))
+    out["c4"] = {"workload": "256x256 CS T=0.7Tc SC+HDM droplet R=48", "steps": c4_steps, "checkpoint_every": every,
+                 "ms_forward_step": round(dt_f / c4_steps * 1e3, 3),
+                 "ms_gradient_per_step": round(dt_g / c4_steps * 1e3, 3),
+                 "note": "gradient = checkpointed forward + reverse sweep of J over the sample"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +560,7 @@ def main():
     curve = size_curve((2048, 8192), args.curve_steps) if args.curve_steps > 0 and args.workload == "c5" else None
     probe = copy_probe(kinds=("mul", "copy", "read", "write")) if args.curve_steps > 0 else None
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
+    cpu_cfg = oracle_configs() if args.cpu_steps > 0 and args.workload == "c5" else None
     kname = KERNEL_NAMES.get(args.variant, "k_march")
     traffic = traffic_from_profile(kname, args.workload, args.prec)
     line = {
@@ -543,6 +588,8 @@ def main():
         line["long_run"] = long_cmp
     if curve:
         line["size_curve"] = curve
+    if cpu_cfg:
+        line["cpu_baseline_configs"] = cpu_cfg
     if probe:
         line["copy_probe"] = probe
         sm = stream_model(kname, args.workload, args.prec, probe, r["launch_ms_mean"])

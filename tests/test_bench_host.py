@@ -82,3 +82,15 @@ def test_kernel_hash_covers_the_kernel_sources():
             h.update(fh.read())
     assert bench.kernel_hash() == h.hexdigest()[:16]
     assert "lbm_march.hpp" in bench.KERNEL_SOURCES and "lbm_device.hpp" in bench.KERNEL_SOURCES
+
+
+def test_oracle_config_timings_shape():
+    """The oracle timings of the other configurations (tiny samples here):
+    every entry present, positive rates, the thread count the oracle used."""
+    out = bench.oracle_configs(c1_steps=4, c2_steps=1, c4_steps=2, every=1)
+    assert out["kind"] == "oracle" and out["cores"] >= 1
+    assert out["c1"]["steps"] == 4 and out["c1"]["mlups"] > 0
+    assert out["c2"]["steps"] == 1 and out["c2"]["mlups"] > 0
+    c4 = out["c4"]
+    assert c4["steps"] == 2 and c4["checkpoint_every"] == 1
+    assert c4["ms_forward_step"] > 0 and c4["ms_gradient_per_step"] > c4["ms_forward_step"]
