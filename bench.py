@@ -523,9 +523,6 @@ def main():
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe()}), flush=True)
         return
-    if args.gpus > 1:
-        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
-        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
