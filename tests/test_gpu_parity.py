@@ -166,8 +166,9 @@ def test_march_forces(eos, force):
 @pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
 def test_march_forces_eight_row_blocks(force, prec):
     """Every force on the marching kernel with 8-row blocks (the default; with
-    FP64 populations the next block's populations are loaded one phase
-    earlier), both population precisions, short and long x axes."""
+    FP64 populations the next block's populations are loaded at the top of the
+    block, for the hybrid force at the start of the collision phase), both
+    population precisions, short and long x axes."""
     for nx, ny in ((40, 100), (140, 88)):
         po, rho0, ux0, uy0 = variant_case("pr", force, nx, ny, seed=3 * nx + ny)
         ref = oracle_run(po, rho0, 30, ux0, uy0)
