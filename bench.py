@@ -372,7 +372,7 @@ def droplet_report(steps: int):
     import numpy as np
 
     import paper_1712_06079_amd as L
-    out = {}
+    out, rhos = {}, {}
     for prec in ("f64", "f32"):
         d, p, desc = _domain("c2", prec)
         rv, rl, _ = L.maxwell(p, p.T)
@@ -389,11 +389,53 @@ def droplet_report(steps: int):
                      "roofline_frac": round(mlups * 1e6 * 2 * Q * es / (HBM_PEAK_GBS * 1e9), 4),
                      "max_v": float(m["totals"][3]), "dp": dp, "R_eff": round(reff, 3), "sigma_L": dp * reff,
                      "mass": float(m["totals"][0]), "finite": d.check_finite()}
+        rhos[prec] = rho
         print(f"[bench] c2 {prec}: {mlups:.0f} MLUPS, max|v| {out[prec]['max_v']:.3e}, dp {dp:.4e}, "
               f"R_eff {reff:.2f}, sigma_L {dp * reff:.4e}", file=sys.stderr, flush=True)
         del d
+    out["f32_vs_f64"] = _precision_diff(rhos, out["f64"], out["f32"], ("dp", "sigma_L", "max_v"))
     out["note"] = "1024^2: 168 MB of FP64 state, resident in the 256 MB Infinity Cache (not an HBM roofline case)"
     out["desc"] = desc
+    return out
+
+
+def _precision_diff(rhos, r64, r32, keys=()):
+    """FP32-population run against the FP64 one: largest relative density
+    difference, relative mass difference and the relative differences of the
+    named scalars."""
+    import numpy as np
+    a, b = rhos["f64"], rhos["f32"]
+    out = {"rho_max_rel_diff": float(np.max(np.abs(b - a) / np.abs(a))),
+           "mass_rel_diff": abs(r32["mass"] - r64["mass"]) / abs(r64["mass"])}
+    for k in keys:
+        out[f"{k}_abs_diff"] = abs(r32[k] - r64[k])
+        out[f"{k}_rel_diff"] = abs(r32[k] - r64[k]) / abs(r64[k]) if r64[k] != 0 else None
+    return out
+
+
+def slab_precision(steps: int):
+    """The 64^2 VDW slab (a = 9/49, b = 2/21, T = 0.9 Tc, k = 0.01, SC + HDM,
+    W = 5, noise 1e-4) run `steps` steps with FP64 and with FP32 populations:
+    the FP32 error against FP64."""
+    import torch
+
+    import paper_1712_06079_amd as L
+    p = L.Params(nx=64, ny=64, eos="vdw", force="sc", a=9 / 49, b=2 / 21, R=1.0, k=0.01, tau=1.0)
+    p.T = 0.9 * L.critical(p)[0]
+    rv, rl, _ = L.maxwell(p, p.T)
+    rho0 = torch.from_numpy(I.slab(64, 64, rv, rl, 5.0, axis="y", noise=1e-4, seed=1)).to("cuda:0")
+    res, rhos = {}, {}
+    for prec in ("f64", "f32"):
+        p.prec = prec
+        d = L.Domain(p, rho0)
+        d.step(steps)
+        m = d.moments()
+        rhos[prec] = m["rho"].cpu().numpy()
+        res[prec] = {"mass": float(m["totals"][0])}
+        del d
+    out = {"workload": "64x64 VDW T=0.9Tc SC+HDM slab", "steps": steps, **_precision_diff(rhos, res["f64"], res["f32"])}
+    print(f"[bench] c1 {steps} steps: f32-vs-f64 max density rel diff {out['rho_max_rel_diff']:.3e}", file=sys.stderr,
+          flush=True)
     return out
 
 
@@ -404,7 +446,7 @@ def long_run_comparison(steps: int):
     import numpy as np
 
     import paper_1712_06079_amd as L
-    res, hist = {}, {}
+    res, hist, rhos = {}, {}, {}
     for prec in ("f64", "f32"):
         d, p, desc = _domain("c5", prec)
         rv, rl, _ = L.maxwell(p, p.T)
@@ -417,10 +459,12 @@ def long_run_comparison(steps: int):
         res[prec] = {"mlups": round(p.nx * p.ny * steps / (ms * 1e-3) / 1e6, 1), "mass": float(tot[0]),
                      "max_v": float(tot[3]), "finite": d.check_finite(), "rho_max": float(rho.max()),
                      "rho_min": float(rho.min())}
-        del d, m, rho
+        rhos[prec] = rho
+        del d, m
     out = {"steps": steps, "desc": desc, "f64": res["f64"], "f32": res["f32"],
            "mass_rel_diff": abs(res["f32"]["mass"] - res["f64"]["mass"]) / abs(res["f64"]["mass"]),
-           "hist_l1": float(np.abs(hist["f32"] - hist["f64"]).sum())}
+           "hist_l1": float(np.abs(hist["f32"] - hist["f64"]).sum()),
+           "rho_max_rel_diff": float(np.max(np.abs(rhos["f32"] - rhos["f64"]) / np.abs(rhos["f64"])))}
     print(f"[bench] c5 {steps} steps: f32-vs-f64 mass rel diff {out['mass_rel_diff']:.3e}, "
           f"histogram L1 {out['hist_l1']:.3e}", file=sys.stderr, flush=True)
     return out
@@ -553,6 +597,7 @@ def main():
         print(f"[bench] adjoint/forward step {adjoint['adjoint_over_forward']}, gradient/forward "
               f"{adjoint['gradient_over_forward']}", file=sys.stderr, flush=True)
     droplet = droplet_report(args.droplet_steps) if args.droplet_steps > 0 else None
+    slab = slab_precision(2000) if args.droplet_steps > 0 else None
     long_cmp = long_run_comparison(args.long_steps) if args.long_steps > 0 and args.workload == "c5" else None
     curve = size_curve((2048, 8192), args.curve_steps) if args.curve_steps > 0 and args.workload == "c5" else None
     probe = copy_probe(kinds=("mul", "copy", "read", "write")) if args.curve_steps > 0 else None
@@ -581,6 +626,8 @@ def main():
         line["adjoint"] = adjoint
     if droplet:
         line["droplet_c2"] = droplet
+    if slab:
+        line["slab_c1_precision"] = slab
     if long_cmp:
         line["long_run"] = long_cmp
     if curve:
