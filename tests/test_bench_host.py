@@ -94,3 +94,17 @@ def test_oracle_config_timings_shape():
     c4 = out["c4"]
     assert c4["steps"] == 2 and c4["checkpoint_every"] == 1
     assert c4["ms_forward_step"] > 0 and c4["ms_gradient_per_step"] > c4["ms_forward_step"]
+
+
+def test_precision_diff_arithmetic():
+    """The FP32-against-FP64 summary: largest relative density difference,
+    relative mass difference, scalar differences (relative only when the FP64
+    value is non-zero)."""
+    import numpy as np
+    rhos = {"f64": np.array([[1.0, 2.0], [4.0, 8.0]]), "f32": np.array([[1.0, 2.002], [4.0, 7.9]])}
+    out = bench._precision_diff(rhos, {"mass": 15.0, "dp": 2.0, "z": 0.0}, {"mass": 14.902, "dp": 2.5, "z": 1e-9},
+                                ("dp", "z"))
+    assert out["rho_max_rel_diff"] == pytest.approx(0.1 / 8.0)
+    assert out["mass_rel_diff"] == pytest.approx(0.098 / 15.0)
+    assert out["dp_abs_diff"] == pytest.approx(0.5) and out["dp_rel_diff"] == pytest.approx(0.25)
+    assert out["z_abs_diff"] == pytest.approx(1e-9) and out["z_rel_diff"] is None
