@@ -468,6 +468,40 @@ def pin_tangent_matches_differences():
     assert np.max(np.abs(fd - jvp)) < 1e-6 * np.max(np.abs(jvp)), np.max(np.abs(fd - jvp))
 
 
+# ------------------------------------------------------------------ Sec. 2, Eq. 9
+def pin_hybrid_limits():
+    """Eq. 9, F = A F^ZC + (1 - 2A) F^SC, at its two exact limits.  A = 0 is the
+    Shan-Chen force.  A = 1/2 leaves half the Zhang-Chen force, -grad U / 2; U
+    is linear in the multiplier g and the periodic derivative is linear in U,
+    so that is the Zhang-Chen force at g/2.  Halving is exact in binary floating
+    point, so both limits hold bitwise over many steps, and in one reverse step
+    (there dJ/dg of the hybrid at g is half that of Zhang-Chen at g/2, since
+    F_hyb(g) = F_ZC(g/2))."""
+    rng = np.random.default_rng(33)
+    for eos, grad in (("cs", "hdm"), ("vdw", "hdm"), ("pr", "cdm")):
+        base, f, rho0, _, _ = _adjoint_case(eos, "sc", grad, nx=13, ny=11)
+
+        def with_(**kw):
+            q = O.Params(**{k: getattr(base, k) for k in base.__dataclass_fields__})
+            for key, v in kw.items():
+                setattr(q, key, v)
+            return q
+
+        g = 0.9
+        h0, sc = with_(force="hybrid", A=0.0, g=g), with_(force="sc", g=g)
+        h5, zc = with_(force="hybrid", A=0.5, g=g), with_(force="zc", g=g / 2)
+        assert np.array_equal(O.run(h0, f, 20), O.run(sc, f, 20)), (eos, grad, "A = 0")
+        assert np.array_equal(O.run(h5, f, 20), O.run(zc, f, 20)), (eos, grad, "A = 1/2")
+        lam = rng.standard_normal(f.shape)
+        l_h0, g_h0 = O.adjoint_step(h0, f, lam)
+        l_sc, g_sc = O.adjoint_step(sc, f, lam)
+        assert np.array_equal(l_h0, l_sc) and np.array_equal(g_h0, g_sc), (eos, grad, "adjoint A = 0")
+        l_h5, g_h5 = O.adjoint_step(h5, f, lam)
+        l_zc, g_zc = O.adjoint_step(zc, f, lam)
+        assert np.array_equal(l_h5, l_zc), (eos, grad, "adjoint A = 1/2")
+        assert g_h5[0] == 0.5 * g_zc[0] and g_h5[1] == g_zc[1], (eos, grad, g_h5, g_zc)
+
+
 # ------------------------------------------------------------------ adjoint
 def _adjoint_case(eos="cs", force="sc", grad="hdm", nx=14, ny=11, tr=0.7, seed=3, tau=0.8):
     p = eos_params(eos)
@@ -576,6 +610,6 @@ FAST = [
     pin_edm_collision, pin_streaming_shift, pin_mass_momentum_conservation, pin_uniform_fixed_point,
     pin_x_invariance, pin_shift_equivariance, pin_mirror_symmetry, pin_shear_wave_viscosity,
     pin_flat_interface_equilibrium, pin_tangent_matches_differences, pin_adjoint_dot_product,
-    pin_adjoint_finite_differences, pin_adjoint_checkpoint_invariance,
+    pin_adjoint_finite_differences, pin_adjoint_checkpoint_invariance, pin_hybrid_limits,
 ]
 SLOW = [pin_maxwell_equal_area, pin_hdm_beats_cdm_coexistence, pin_table1_laplace]

@@ -1,8 +1,10 @@
 """Plant plausible mistakes in copies of the oracle and check that the pins catch them.
 
 Each mutant is one textual change to ``oracle/lbm_oracle.cpp`` (a dropped term,
-a wrong sign, coefficient, index or operand), compiled on the CPU into a
-temporary library.  The fast pins then run against that build; at least one
+a wrong sign, coefficient, index or operand; every occurrence of the pattern is
+replaced, and a mutant given as a list of changes applies all of them, so that
+the same mistake can be planted in the forward step and in its adjoint),
+compiled on the CPU into a temporary library.  The fast pins then run against that build; at least one
 must fail.  Nothing here touches the GPU.
 """
 import os
@@ -67,6 +69,15 @@ MUTANTS = {
                            "lam[k * N + c] = (1.0 - 1.0 / tau) * mu[k] + rb + EX[k] * jbx_ + EX[k] * jby_;"),
     "adjoint_dA_dm": ("*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 3.0 * mx) / rho);", "*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 1.5 * mx) / rho);"),
     "dp_drho_cs": ("return R * T * (Z + e * Zp) - 2.0 * a * rho;", "return R * T * (Z + Zp) - 2.0 * a * rho;"),
+    # Eq. 9 weights, changed consistently in the forward force and its adjoint
+    # (a mistake made in both passes survives the dot-product identity)
+    "hybrid_sc_weight_both_passes": ("(1.0 - 2.0 * m.p.A)", "(1.0 - m.p.A)"),
+    "hybrid_weights_swapped_both_passes": [
+        ("w.Fx[c] = m.p.A * fzx + (1.0 - 2.0 * m.p.A) * fsx;", "w.Fx[c] = (1.0 - 2.0 * m.p.A) * fzx + m.p.A * fsx;"),
+        ("w.Fy[c] = m.p.A * fzy + (1.0 - 2.0 * m.p.A) * fsy;", "w.Fy[c] = (1.0 - 2.0 * m.p.A) * fzy + m.p.A * fsy;"),
+        ("const double wsc = (m.p.force == 2) ? (1.0 - 2.0 * m.p.A) : 1.0;", "const double wsc = (m.p.force == 2) ? m.p.A : 1.0;"),
+        ("const double wzc = (m.p.force == 2) ? m.p.A : 1.0;", "const double wzc = (m.p.force == 2) ? (1.0 - 2.0 * m.p.A) : 1.0;"),
+    ],
 }
 
 
@@ -75,11 +86,14 @@ def builds():
     tmp = tempfile.mkdtemp(prefix="oracle_mut_")
     src = open(SRC).read()
     libs, procs = {}, []
-    for name, (old, new) in MUTANTS.items():
-        assert old in src, f"mutant {name}: pattern not found in the oracle source"
+    for name, change in MUTANTS.items():
+        text = src
+        for old, new in (change if isinstance(change, list) else [change]):
+            assert old in text, f"mutant {name}: pattern not found in the oracle source"
+            text = text.replace(old, new)
         path = os.path.join(tmp, f"{name}.cpp")
         with open(path, "w") as fh:
-            fh.write(src.replace(old, new))
+            fh.write(text)
         lib = os.path.join(tmp, f"lib{name}.so")
         procs.append((name, lib, subprocess.Popen(
             ["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-o", lib, path])))
