@@ -85,6 +85,11 @@ def _make_workload(name: str, seed: int):
 
 
 def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0, chunks: int = 0):
+    """Time exactly `steps` steps after `warmup` untimed ones with one pair of
+    HIP events around the timed launches, recorded on the stream the library
+    launches on (torch's current stream).  The mean launch duration is that
+    span over `steps`: the launches are back to back, so it is the kernel's
+    average duration plus the (sub-microsecond) gaps between launches."""
     import torch
 
     import paper_1712_06079_amd as L
@@ -96,36 +101,46 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     d.set_kernel(variant, tile)
     d.set_chunks(chunks)
     stream = torch.cuda.current_stream()
-    d.step(warmup)
-    torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    d.step(warmup, stream=stream)
     total0 = torch.cuda.Event(enable_timing=True)
     total1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     total0.record(stream)
-    for i in range(steps):
-        starts[i].record(stream)
-        d.step(1)
-        ends[i].record(stream)
+    d.step(steps, stream=stream)
     total1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_total = total0.elapsed_time(total1)
-    per_launch = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ok = d.check_finite()
     cells = p.nx * p.ny
     mlups = cells * steps / (ms_total * 1e-3) / 1e6
     es = 8 if prec == "f64" else 4
     alg_bytes = 2 * Q * es * cells  # per launch
-    launch_s = float(np.mean(per_launch)) * 1e-3
-    achieved = alg_bytes / launch_s / 1e9
+    launch_ms = ms_total / steps
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     return {
         "desc": desc, "params": p, "mlups": mlups, "ms_per_step": ms_total / steps, "wall_s": wall,
-        "launch_ms_mean": float(np.mean(per_launch)), "launch_ms_median": float(np.median(per_launch)),
-        "achieved_gbs": achieved, "alg_bytes_per_launch": alg_bytes, "finite": ok,
+        "launch_ms_mean": launch_ms, "achieved_gbs": achieved, "alg_bytes_per_launch": alg_bytes, "finite": ok,
+        "domain": d,
     }
+
+
+def steady_state(r, steps: int):
+    """The same domain stepped `steps` more steps right after the headline
+    window (one event pair): the steady-state rate of the same kernel."""
+    import torch
+    d, p = r["domain"], r["params"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    d.step(steps, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    es = 8 if p.prec == "f64" else 4
+    return {"steps": steps, "ms_per_step": round(ms, 5), "mlups": round(p.nx * p.ny / (ms * 1e-3) / 1e6, 1),
+            "roofline_frac": round(2 * Q * es * p.nx * p.ny / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def traffic_from_profile(kernel: str, name: str, prec: str):
@@ -305,34 +320,63 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
 
 
 def copy_probe(gib: float = 2.0, reps: int = 20, kinds=("mul",)):
-    """Plain streaming kernels of known size (FP64 arrays of `gib` GiB): "mul"
-    is dst = 1.0 * src (the kernel the counter calibration uses), "copy" is
-    dst.copy_(src) (both read and write `gib` GiB), "read" is src.sum() (reads
-    only), "write" is dst.fill_(1) (writes only).  Their rates are the
-    attainable HBM bandwidth the fused step is compared with; on HBM3E reads
-    stream markedly faster than writes."""
+    """torch's dst = 1.0 * src over FP64 arrays of `gib` GiB (reads and writes
+    `gib` GiB per launch): the kernel the rocprofv3 byte-counter calibration
+    was taken on."""
     import torch
     n = int(gib * (1 << 30) / 8)
     src = torch.rand(n, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
-    ops = {"mul": lambda: torch.mul(src, 1.0, out=dst), "copy": lambda: dst.copy_(src),
-           "read": lambda: src.sum(), "write": lambda: dst.fill_(1.0)}
-    factor = {"mul": 2, "copy": 2, "read": 1, "write": 1}
     out = {}
     for kind in kinds:
-        f = ops[kind]
         for _ in range(3):
-            f()
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            f()
+            torch.mul(src, 1.0, out=dst)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        moved = factor[kind] * n * 8
+        moved = 2 * n * 8
         out[kind] = {"bytes_per_launch": moved, "ms": round(ms, 4), "GBps": round(moved / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
+PROBE_GRIDS = (1024, 2048, 4096, 8192, 16384, 32768)
+
+
+def stream_probe(gib: float = 2.0, reps: int = 10, grids=PROBE_GRIDS):
+    """The library's hand-written streaming kernels (lbm_stream_probe: 16-byte
+    non-temporal accesses) over `gib` GiB: copy (reads and writes `gib` GiB),
+    read-only and write-only, each at the best of a sweep of grid sizes.  Their
+    rates are the attainable HBM bandwidth the fused step is compared with."""
+    import torch
+
+    import paper_1712_06079_amd as L
+    nbytes = int(gib * (1 << 30)) // 16 * 16
+    src = torch.rand(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    factor = {"copy": 2, "read": 1, "write": 1}
+    out = {}
+    for kind in ("copy", "read", "write"):
+        best = None
+        for g in grids:
+            L.stream_probe(kind, src, dst, g)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                L.stream_probe(kind, src, dst, g)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbps = factor[kind] * nbytes / (ms * 1e-3) / 1e9
+            if best is None or gbps > best["GBps"]:
+                best = {"bytes_per_launch": factor[kind] * nbytes, "ms": round(ms, 4), "GBps": round(gbps, 1), "grid": g}
+        out[kind] = best
+    out["kernel"] = "lbm_stream_probe (paper_1712_06079_amd/csrc/lbm_probe.hip)"
     return out
 
 
@@ -486,8 +530,18 @@ def size_curve(sizes, steps: int):
     return out
 
 
-def cpu_baseline(name: str, sample_steps: int):
-    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(name: str, sample_steps: int):
     import oracle as O
     p, rho0, ux0, uy0, _ = workload(name)
     po = O.Params(nx=p.nx, ny=p.ny, eos=p.eos, force=p.force, grad=p.grad, tau=p.tau, a=p.a, b=p.b, R=p.R,
@@ -496,8 +550,29 @@ def cpu_baseline(name: str, sample_steps: int):
     t0 = time.perf_counter()
     O.run(po, f, sample_steps)
     dt = time.perf_counter() - t0
-    return {"value": round(p.nx * p.ny * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.threads(),
-            "kind": "oracle", "sample": f"{sample_steps} FP64 steps of the {p.nx}x{p.ny} workload ({dt:.1f} s)"}
+    return p, dt, O.threads()
+
+
+def cpu_baseline(name: str, sample_steps: int, single_steps: int = 4):
+    """The FP64 oracle on a bounded sample of the same workload: on every host
+    core (OpenMP over lines and cells) and, in a child process with one
+    OpenMP thread, on a shorter sample."""
+    import subprocess
+    p, dt, cores = _oracle_sample(name, sample_steps)
+    out = {"value": round(p.nx * p.ny * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+           "kind": "oracle", "sample": f"{sample_steps} FP64 steps of the {p.nx}x{p.ny} workload ({dt:.1f} s)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if single_steps > 0:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        code = (f"import json, bench; p, dt, c = bench._oracle_sample({name!r}, {single_steps}); "
+                f"print(json.dumps([p.nx * p.ny * {single_steps} / dt / 1e6, dt, c]))")
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode == 0:
+            v, dt1, c1 = json.loads(r.stdout.strip().splitlines()[-1])
+            out["one_thread"] = {"value": round(v, 3), "unit": "MLUPS", "cores": c1,
+                                 "sample": f"{single_steps} FP64 steps of the {p.nx}x{p.ny} workload ({dt1:.1f} s)"}
+    return out
 
 
 def oracle_configs(c1_steps: int = 2000, c2_steps: int = 200, c4_steps: int = 140, every: int = 70):
@@ -558,6 +633,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=64, help="oracle sample steps (0 = skip)")
     ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-probe", action="store_true", help="only run the streaming-copy calibration kernel")
+    ap.add_argument("--no-probe", dest="probe", action="store_false", help="skip the streaming probes")
+    ap.add_argument("--steady-steps", type=int, default=2000,
+                    help="steps timed right after the headline window on the same domain (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
     ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
@@ -574,18 +652,35 @@ def main():
         print("bench.py: launched with WORLD_SIZE > 1; the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
+    # The streaming probe runs first: besides the attainable rates it reports,
+    # its second of memory traffic takes the device out of the power state it
+    # idles in.  From idle, launches 5-25 of the step run 10-20 % slower than
+    # in steady state (a transient of the device, not of the kernel), which a
+    # short timed window right after a few warm-up steps would measure.
+    probe = stream_probe() if args.probe else None
+    if probe:
+        print(f"[bench] streaming probe: copy {probe['copy']['GBps']:.0f}, read {probe['read']['GBps']:.0f}, "
+              f"write {probe['write']['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile, args.chunks)
     print(f"[bench] {args.workload} {args.prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
-          f"kernel {r['launch_ms_mean']:.4f} ms, {r['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+          f"{r['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    steady = steady_state(r, args.steady_steps) if args.steady_steps > 0 else None
+    if steady:
+        print(f"[bench] steady state over {args.steady_steps} more steps: {steady['mlups']:.0f} MLUPS",
+              file=sys.stderr, flush=True)
+    del r["domain"]
     p = r["params"]
     other = None
     if not args.no_other_prec:
         op = "f32" if args.prec == "f64" else "f64"
         o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile, args.chunks)
-        print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, kernel {o['launch_ms_mean']:.4f} ms, "
+        print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, {o['ms_per_step']:.4f} ms/step, "
               f"{o['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+        osteady = steady_state(o, args.steady_steps) if args.steady_steps > 0 else None
+        del o["domain"]
         other = {"storage": op, "dtype": "f64", "value": round(o["mlups"], 1), "ms_per_step": round(o["ms_per_step"], 5),
-                 "roofline_frac": round(o["achieved_gbs"] / HBM_PEAK_GBS, 4), "finite": o["finite"]}
+                 "roofline_frac": round(o["achieved_gbs"] / HBM_PEAK_GBS, 4), "finite": o["finite"],
+                 "steady_state": osteady}
     batch = None
     if args.batch_steps > 0:
         batch = batch_sweep(args.batch_steps, max(args.batch_steps // 10, 20))
@@ -600,11 +695,18 @@ def main():
     slab = slab_precision(2000) if args.droplet_steps > 0 else None
     long_cmp = long_run_comparison(args.long_steps) if args.long_steps > 0 and args.workload == "c5" else None
     curve = size_curve((2048, 8192), args.curve_steps) if args.curve_steps > 0 and args.workload == "c5" else None
-    probe = copy_probe(kinds=("mul", "copy", "read", "write")) if args.curve_steps > 0 else None
+    calib = copy_probe() if args.probe else None
     cpu = cpu_baseline(args.workload, args.cpu_steps) if args.cpu_steps > 0 else None
     cpu_cfg = oracle_configs() if args.cpu_steps > 0 and args.workload == "c5" else None
     kname = KERNEL_NAMES.get(args.variant, "k_march")
     traffic = traffic_from_profile(kname, args.workload, args.prec)
+    roof = {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kname, "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+            "launch_ms": round(r["launch_ms_mean"], 5)}
+    if probe:
+        roof["attainable"] = {"kind": "copy", "GBps": probe["copy"]["GBps"],
+                              "frac": round(r["achieved_gbs"] / probe["copy"]["GBps"], 4), "kernel": "lbm_stream_probe"}
     line = {
         "metric": METRIC, "value": round(r["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
@@ -612,12 +714,11 @@ def main():
         "config": {"workload": r["desc"], "storage": args.prec, "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
                    "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": kname,
                    "finite": r["finite"]},
-        "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": kname, "alg_bytes_per_launch": r["alg_bytes_per_launch"],
-                     "launch_ms": round(r["launch_ms_mean"], 5)},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if steady:
+        line["steady_state"] = steady
     if other:
         line["other_precision"] = other
     if batch:
@@ -635,10 +736,12 @@ def main():
     if cpu_cfg:
         line["cpu_baseline_configs"] = cpu_cfg
     if probe:
-        line["copy_probe"] = probe
+        line["stream_probe"] = probe
         sm = stream_model(kname, args.workload, args.prec, probe, r["launch_ms_mean"])
         if sm:
             line["stream_model"] = sm
+    if calib:
+        line["counter_calibration_kernel"] = calib
     print(json.dumps(line), flush=True)
 
 

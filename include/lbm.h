@@ -104,7 +104,12 @@ lbm_status lbm_maxwell(const lbm_params* p, double T, double* rho_v, double* rho
  * hold 40 doubles. */
 lbm_status lbm_hdm_row(int32_t n, int32_t prec, double* d, int32_t* taps);
 
-/* Device workspace needed by one domain with these parameters (bytes). */
+/* Device workspace needed by one domain with these parameters (bytes): two
+ * population buffers f[9] per site (Sec. 2, Eqs. 1-3; FP64 or FP32 storage),
+ * two planes of the potential field (Phi of Eq. 21 signed, or U of Eq. 8),
+ * reduction partials and the coefficient tables of the Eq. 20 stencil
+ * (Sec. 3.2).  Host, synchronous; LBM_EINVAL for invalid parameters or a NULL
+ * `bytes`. */
 lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
 
 /* Create a domain in `workspace` (device, >= lbm_workspace_bytes, 256-byte
@@ -117,7 +122,14 @@ lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
 lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes, const double* rho0,
                     const double* ux0, const double* uy0, hipStream_t stream, lbm_domain** out);
 
-/* Advance the domain by nsteps >= 0 time steps (asynchronous). */
+/* Advance the domain by nsteps >= 0 time steps (asynchronous): each step is
+ * Sec. 2 Eq. 1 with the density and momentum of Eq. 3, the potential of Eq. 8
+ * / Eq. 21 (Hu's scaling, Sec. 5), the gradient of Eq. 20 (Sec. 3.2; or
+ * Eq. 14 / Eq. 15 of Sec. 3.1), the force of Eq. 22, Eq. 7 or Eq. 9, the
+ * exact-difference forcing of Eq. 10 with the equilibrium of Eq. 2, and
+ * periodic streaming.  LBM_EINVAL for a NULL domain or nsteps < 0,
+ * LBM_EUNSUPPORTED when the selected kernel variant cannot run this domain;
+ * launch failures return LBM_EDEVICE. */
 lbm_status lbm_step(lbm_domain* d, int64_t nsteps, hipStream_t stream);
 
 /* Output moments of the current state (asynchronous): rho (Eq. 3), the
@@ -160,8 +172,11 @@ lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
  * workgroups), otherwise min(nchunk, ny).  LBM_EINVAL for nchunk < 0. */
 lbm_status lbm_set_chunks(lbm_domain* d, int32_t nchunk);
 
-/* Check the current density for non-finite values (synchronises `stream`):
- * *ok = 1 if every rho is finite, else 0 (and the call returns LBM_ENONFINITE). */
+/* Check the current density (Eq. 3) for non-finite values (synchronises
+ * `stream`): *ok = 1 if every rho is finite, else 0 (and the call returns
+ * LBM_ENONFINITE).  A non-finite density is how a run that has left the
+ * stable range of Hu's scaling (Sec. 5) shows itself.  LBM_EINVAL for NULL
+ * arguments. */
 lbm_status lbm_check_finite(lbm_domain* d, int32_t* ok, hipStream_t stream);
 
 /* ---- state snapshots (checkpoint / restart) ------------------------------ */
@@ -241,8 +256,10 @@ lbm_status lbm_batch_workspace_bytes(const lbm_params* params, int32_t n, size_t
 lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace, size_t workspace_bytes,
                             const double* const* rho0s, hipStream_t stream, lbm_batch** out);
 
-/* Advance every domain by nsteps: one batched launch per step, in captured
- * graphs of 16 launches (asynchronous). */
+/* Advance every domain by nsteps (the step of lbm_step: Sec. 2 Eq. 1 with
+ * Eqs. 2, 3, 8, 10, 20-22): one batched launch per step, in captured graphs of
+ * 16 launches (asynchronous).  LBM_EINVAL for a NULL batch or nsteps < 0;
+ * LBM_EDEVICE if a graph cannot be captured or launched. */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, hipStream_t stream);
 
 /* The same evolution with one single-domain fused launch per domain per step
@@ -274,6 +291,19 @@ void lbm_batch_destroy(lbm_batch* b);
 
 /* Free the host state of a domain (the workspace stays with the caller). */
 void lbm_destroy(lbm_domain* d);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+/* Streaming probe (asynchronous): one launch of a plain hand-written kernel
+ * that measures the HBM rate attainable on the device, the practical ceiling
+ * beside the 8 TB/s peak for the bandwidth-bound step.  16-byte elements with
+ * non-temporal loads and stores, a grid-stride loop over `grid` workgroups of
+ * 256 threads.  kind 0 copy (dst = src, reads and writes `bytes`), 1 read
+ * (reads `bytes` of src, writes one double per workgroup to dst, which must
+ * hold `grid` doubles), 2 write (dst = 1.0, writes `bytes`; src unused).
+ * Device buffers 16-byte aligned, bytes a positive multiple of 16, grid in
+ * [1, 2^24]; LBM_EINVAL otherwise. */
+lbm_status lbm_stream_probe(int32_t kind, const void* src, void* dst, size_t bytes, int32_t grid, hipStream_t stream);
 
 /* Thread-local description of the last failure in this thread. */
 const char* lbm_last_error(void);

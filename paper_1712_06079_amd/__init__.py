@@ -12,7 +12,8 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
-__all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxwell", "hdm_row", "EOS", "FORCE", "GRAD", "PREC"]
+__all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxwell", "hdm_row", "stream_probe", "EOS",
+           "FORCE", "GRAD", "PREC"]
 
 EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
 FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
@@ -93,13 +94,14 @@ def library():
         L.lbm_adjoint_rho0.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
         L.lbm_record.argtypes = [_VP, C.c_int64, _VP, C.c_size_t, _VP]
         L.lbm_adjoint_steps.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+        L.lbm_stream_probe.argtypes = [C.c_int32, _VP, _VP, C.c_size_t, C.c_int32, _VP]
         L.lbm_destroy.argtypes = [_VP]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
                    "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
-                   "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps"):
+                   "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps", "lbm_stream_probe"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -145,6 +147,18 @@ def _stream(stream):
     torch = _torch()
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+PROBE_KINDS = {"copy": 0, "read": 1, "write": 2}
+
+
+def stream_probe(kind: str, src, dst, grid: int, stream=None):
+    """One launch of the library's streaming probe (lbm_stream_probe): "copy"
+    dst = src, "read" (dst receives one double per workgroup), "write" dst = 1;
+    src / dst are CUDA tensors, the moved size is src's (dst's for "write")."""
+    t = dst if kind == "write" else src
+    nbytes = t.numel() * t.element_size()
+    check(library().lbm_stream_probe(PROBE_KINDS[kind], _ptr(src), _ptr(dst), nbytes, int(grid), _stream(stream)))
 
 
 class Domain:

@@ -11,6 +11,7 @@
 #include "../../include/lbm.h"
 #include "hdm_coeffs.hpp"
 #include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
 
 // Host state of one domain: parameters, planned constants, coefficient rows and
 // the layout of its caller-owned workspace.

@@ -80,7 +80,8 @@ def test_c1_fp64(c1_oracle, variant, tile):
 
 
 def test_c1_fp32(c1_oracle):
-    """The same run with FP32 populations and arithmetic: densities within 1e-5."""
+    """The same run with FP32 population storage (arithmetic stays FP64):
+    densities within 1e-5 of the FP64 oracle."""
     po, rho0, ref = c1_oracle
     got = gpu_run(po, rho0, 2000, "f32")
     err = rel_err(got["rho"], ref["rho"])
@@ -208,19 +209,33 @@ def test_cdm_gradient():
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_moments_match_oracle(prec):
-    """Half-step velocity (Eq. 11), bulk pressure and the fixed-order totals."""
+    """Half-step velocity (Eq. 11), bulk pressure and the fixed-order totals,
+    element by element.  v = (j + F/2) / rho is a difference of sums of size
+    rho (j sums the positive populations with signs) plus the force, so its
+    error at a site is bounded by the tolerance times (rho + |F|) / rho; the
+    bulk pressure p = rho/3 + U(rho) by the tolerance times
+    rho/3 + |U| + rho |dU/drho| (the density error carried through U)."""
     po, rho0, ux0, uy0 = variant_case("vdw", "sc", 96, 80, seed=4)
     ref = oracle_run(po, rho0, 100, ux0, uy0)
     got = gpu_run(po, rho0, 100, prec, ux0, uy0)
     tol = TOL[prec]
-    vscale = max(np.abs(ref["vx"]).max(), np.abs(ref["vy"]).max())
-    assert np.max(np.abs(got["vx"] - ref["vx"])) < 50 * tol * vscale
-    assert np.max(np.abs(got["vy"] - ref["vy"])) < 50 * tol * vscale
-    assert np.max(np.abs(got["p"] - ref["p"])) < 10 * tol * np.abs(ref["p"]).max()
+    rho = ref["rho"]
+    for c in ("x", "y"):
+        bound = 4 * tol * (rho + np.abs(ref["F" + c])) / rho
+        worst = float(np.max(np.abs(got["v" + c] - ref["v" + c]) / bound))
+        print(f"v{c}: worst error / bound {worst:.3f}")
+        assert worst < 1.0
+    U = ref["p"] - rho / 3
+    dU = np.array([po.g * (po.k * O.eos(po, float(r), po.T)[1] - 1 / 3) for r in rho.ravel()]).reshape(rho.shape)
+    bound = 4 * tol * (rho / 3 + np.abs(U) + rho * np.abs(dU))
+    worst = float(np.max(np.abs(got["p"] - ref["p"]) / bound))
+    print(f"p: worst error / bound {worst:.3f}")
+    assert worst < 1.0
     t = got["totals"]
-    assert abs(t[0] / ref["rho"].sum() - 1) < tol
+    assert abs(t[0] / rho.sum() - 1) < tol
     vmax = np.hypot(ref["vx"], ref["vy"]).max()
-    assert abs(t[3] / vmax - 1) < 50 * tol
+    vb = 4 * tol * float(np.max((rho + np.hypot(ref["Fx"], ref["Fy"])) / rho))
+    assert abs(t[3] - vmax) < vb
 
 
 def test_x_invariance_bitwise():
