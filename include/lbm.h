@@ -65,8 +65,10 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
  *          alpha = 1/sqrt(T)), RKS (Eq. 27 with the Soave alpha(T_r))
  *  force   Shan-Chen (Eq. 22), Zhang-Chen (Eq. 7), hybrid (Eq. 9, weight A)
  *  grad    HDM (Eq. 20) or central difference (Eq. 14)
- *  prec    storage precision of the populations (FP64 or FP32); the potential
- *          field and all arithmetic are FP64 in both cases
+ *  prec    storage precision of the populations (FP64 or FP32); all arithmetic
+ *          is FP64.  The potential field is stored in FP64, except with FP32
+ *          populations and the Shan-Chen or Zhang-Chen force, where it is
+ *          stored in FP32
  *  tau     relaxation time (Eq. 1), > 1/2
  *  a,b,R   EOS constants; omega is the acentric factor (PR, RKS)
  *  T       absolute temperature (T_r = T / Tc; see lbm_critical)

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
-    stage_cross<double, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    stage_cross<double, TY>(s, static_cast<const double*>(a.phi_in), x0, y0, a.nx, a.ny, pitch);
     __syncthreads();
     constexpr int J = Cross<double, TY>::J;
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         if (FORCE == FORCE_ZC) {
             ub = dxa + dya;
         } else {
-            const double ph = a.phi_in[op];
+            const double ph = static_cast<const double*>(a.phi_in)[op];
             const double sgn = ph < 0.0 ? -1.0 : 1.0;
             ub = A.ubl[op] + sgn / (2.0 * fabs(ph)) * (-dxa - dya);
         }

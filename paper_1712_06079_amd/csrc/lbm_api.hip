@@ -76,7 +76,7 @@ Layout layout_of(const lbm_params* p) {
     const size_t pitch = (size_t)nblocks_x(p->nx) * lbm::BX;
     Layout L;
     L.f = align256(lbm::Q * pitch * p->ny * es);
-    L.phi = align256(pitch * p->ny * sizeof(double));
+    L.phi = align256(pitch * p->ny * phi_elem_bytes(p));
     const size_t nb = (size_t)nblocks_x(p->nx) * ((p->ny + MOM_TY - 1) / MOM_TY);
     L.part = align256(nb * 4 * sizeof(double));
     L.scr = 256;
@@ -168,7 +168,7 @@ int auto_tile(const lbm_domain* d) {
     return ty;
 }
 
-lbm_status run_step(lbm_domain* d, const void* f_in, const double* phi_in, void* f_out, double* phi_out, hipStream_t s) {
+lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f_out, void* phi_out, hipStream_t s) {
     if (d->variant == 3 && !march_eligible(d))
         return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and a longer y axis (ny = %d)", d->p.ny);
     lbm_status st = LBM_OK;
@@ -210,8 +210,8 @@ lbm_status run_step(lbm_domain* d, const void* f_in, const double* phi_in, void*
 
 lbm_status step_once(lbm_domain* d, hipStream_t s) {
     const int in = d->cur, out = 1 - d->cur;
-    lbm_status st = run_step(d, d->ws + d->off_f[in], reinterpret_cast<const double*>(d->ws + d->off_phi[in]),
-                             d->ws + d->off_f[out], reinterpret_cast<double*>(d->ws + d->off_phi[out]), s);
+    lbm_status st = run_step(d, d->ws + d->off_f[in], d->ws + d->off_phi[in], d->ws + d->off_f[out],
+                             d->ws + d->off_phi[out], s);
     if (st != LBM_OK) return st;
     d->cur = out;
     return LBM_OK;
@@ -483,7 +483,7 @@ lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride
     for (int64_t t = 0; t < nsteps; ++t) {
         char* in = base + (size_t)t * stride;
         char* out = in + stride;
-        st = run_step(d, in, reinterpret_cast<const double*>(in + fb), out, reinterpret_cast<double*>(out + fb), stream);
+        st = run_step(d, in, in + fb, out, out + fb, stream);
         if (st != LBM_OK) return st;
     }
     if (nsteps > 0) {
@@ -542,7 +542,7 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     std::memset(&A, 0, sizeof(A));
     A.s = make_args<double>(d, d->cur, d->cur);
     A.s.f_in = static_cast<const double*>(state_t);
-    A.s.phi_in = reinterpret_cast<const double*>(static_cast<const char*>(state_t) + f_bytes(d));
+    A.s.phi_in = static_cast<const char*>(state_t) + f_bytes(d);
     A.s.phi_out = nullptr;
     A.ax = reinterpret_cast<double*>(w);
     A.ay = reinterpret_cast<double*>(w + L.plane);

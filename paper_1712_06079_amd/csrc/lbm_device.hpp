@@ -2,12 +2,15 @@
 // gfx950: population layout, EOS potential, equilibrium, collision.
 //
 // Storage and arithmetic: populations are stored as `Real` (double or float),
-// the potential field always as double, and every arithmetic step is carried
-// out in double (values are widened on load and rounded once on store).  On
-// MI355X the FP64 vector rate equals the unpacked FP32 rate and the step is
-// bound by HBM bytes, so FP32 populations halve the dominant traffic without
-// FP32 arithmetic error; the potential field stays FP64 because its rounding
-// would enter the force through the stencil.
+// the potential field as PhiStore<Real, FORCE>::type, and every arithmetic
+// step is carried out in double (values are widened on load and rounded once
+// on store).  On MI355X the FP64 vector rate equals the unpacked FP32 rate and
+// the step is bound by HBM bytes, so FP32 storage cuts the traffic without
+// FP32 arithmetic error.  With FP32 populations the Shan-Chen and Zhang-Chen
+// potential fields are stored in FP32 too (their rounding moves the densities
+// of the 2000-step 64^2 slab by about 1e-6, against the 1e-5 bar); the hybrid
+// force keeps an FP64 field (there the FP32 rounding of both fields it
+// differentiates moved a Peng-Robinson case by 1e-5 in 60 steps).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -160,13 +163,22 @@ struct StepTables {
     double ty_tab[TAB];
 };
 
-// Kernel arguments of one domain step (passed by value).
+// Storage type of the potential field (see the note at the top).
+template <typename Real, int FORCE>
+struct PhiStore { using type = double; };
+template <>
+struct PhiStore<float, FORCE_SC> { using type = float; };
+template <>
+struct PhiStore<float, FORCE_ZC> { using type = float; };
+
+// Kernel arguments of one domain step (passed by value).  The potential
+// planes are untyped here; kernels view them as PhiStore<Real, FORCE>::type.
 template <typename Real>
 struct StepArgs {
     const Real* __restrict__ f_in;
     Real* __restrict__ f_out;
-    const double* __restrict__ phi_in;
-    double* __restrict__ phi_out;
+    const void* __restrict__ phi_in;
+    void* __restrict__ phi_out;
     int nx, ny, nxb;  // lattice size, number of 64-cell x blocks
     int tx, ty;       // one-sided taps used along x and along y
     double omega;     // 1 / tau

@@ -147,6 +147,9 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int nx = a.nx, ny = a.ny, nxb = a.nxb, pitch = nxb * BX;
+    using P = typename PhiStore<Real, FORCE>::type;
+    const P* __restrict__ phin = static_cast<const P*>(a.phi_in);
+    P* __restrict__ phio = static_cast<P*>(a.phi_out);
 
     // Phase 1 loads: the potential cross, issued first because it is needed
     // first (vector loads retire in order, so a wait for the cross must not
@@ -156,12 +159,12 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     stage_issue(srow, tid, [&](int i) {
         const int r = i / S::RW, c = i - r * S::RW;
         const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
-        return a.phi_in[(long)yw * pitch + xw];
+        return (double)phin[(long)yw * pitch + xw];
     });
     stage_issue(scol, tid, [&](int i) {
         const int r = i / CW, c = i - r * CW;
         const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
-        return a.phi_in[(long)yw * pitch + xw];
+        return (double)phin[(long)yw * pitch + xw];
     });
 
     // Keep the compiler from moving cross loads behind population loads.
@@ -279,7 +282,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
                 }
                 double rho, jx, jy;
                 moments(g, rho, jx, jy);
-                a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, rho));
+                phio[(long)y * pitch + x] = (P)phi_of<FORCE>(potential(a.eos, rho));
             }
         }
     }

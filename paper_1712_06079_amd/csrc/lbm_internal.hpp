@@ -54,6 +54,12 @@ inline unsigned grid_1d(long n) {
     return (unsigned)b;
 }
 
+// Bytes per site of a domain's potential field (lbm::PhiStore: FP32 for FP32
+// populations with the Shan-Chen or Zhang-Chen force, otherwise FP64).
+inline size_t phi_elem_bytes(const lbm_params* p) {
+    return (p->prec == LBM_F32 && p->force != LBM_FORCE_HYBRID) ? 4 : 8;
+}
+
 // Kernel arguments of one step of domain d reading buffer in_buf, writing out_buf.
 template <typename Real>
 lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
@@ -61,8 +67,8 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     std::memset(&a, 0, sizeof(a));
     a.f_in = reinterpret_cast<const Real*>(d->ws + d->off_f[in_buf]);
     a.f_out = reinterpret_cast<Real*>(d->ws + d->off_f[out_buf]);
-    a.phi_in = reinterpret_cast<const double*>(d->ws + d->off_phi[in_buf]);
-    a.phi_out = reinterpret_cast<double*>(d->ws + d->off_phi[out_buf]);
+    a.phi_in = d->ws + d->off_phi[in_buf];
+    a.phi_out = d->ws + d->off_phi[out_buf];
     a.nx = d->p.nx;
     a.ny = d->p.ny;
     a.nxb = d->nxb;

@@ -20,6 +20,8 @@ constexpr int NT = 256;  // threads per workgroup (four wavefronts)
 template <typename Real, int FORCE>
 __global__ void __launch_bounds__(NT) k_init(StepArgs<Real> a, const double* __restrict__ rho0,
                                              const double* __restrict__ ux0, const double* __restrict__ uy0) {
+    using P = typename PhiStore<Real, FORCE>::type;
+    P* __restrict__ phio = static_cast<P*>(a.phi_out);
     const int pitch = a.nxb * BX;
     const long total = (long)pitch * a.ny;
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < total; c += (long)gridDim.x * NT) {
@@ -39,17 +41,19 @@ __global__ void __launch_bounds__(NT) k_init(StepArgs<Real> a, const double* __r
             }
             double r, jx, jy;
             moments(fi, r, jx, jy);
-            a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, r));
+            phio[(long)y * pitch + x] = (P)phi_of<FORCE>(potential(a.eos, r));
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[fidx(x, y, i, a.nxb)] = Real(0);
-            a.phi_out[(long)y * pitch + x] = 0.0;
+            phio[(long)y * pitch + x] = P(0);
         }
     }
 }
 
 template <typename Real, int FORCE>
 __global__ void __launch_bounds__(NT) k_phi(StepArgs<Real> a) {
+    using P = typename PhiStore<Real, FORCE>::type;
+    P* __restrict__ phio = static_cast<P*>(a.phi_out);
     const int pitch = a.nxb * BX;
     const long total = (long)pitch * a.ny;
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < total; c += (long)gridDim.x * NT) {
@@ -60,7 +64,7 @@ __global__ void __launch_bounds__(NT) k_phi(StepArgs<Real> a) {
         for (int i = 0; i < Q; ++i) fi[i] = (double)a.f_in[fidx(x, y, i, a.nxb)];
         double r, jx, jy;
         moments(fi, r, jx, jy);
-        a.phi_out[(long)y * pitch + x] = phi_of<FORCE>(potential(a.eos, r));
+        phio[(long)y * pitch + x] = (P)phi_of<FORCE>(potential(a.eos, r));
     }
 }
 
@@ -131,21 +135,21 @@ __device__ inline void stage_lds(double* __restrict__ dst, Src src) {
     }
 }
 
-template <typename Real, int TY>
-__device__ inline void stage_cross(Cross<Real, TY>& s, const double* __restrict__ phi, int x0, int y0, int nx,
+template <typename Real, int TY, typename P>
+__device__ inline void stage_cross(Cross<Real, TY>& s, const P* __restrict__ phi, int x0, int y0, int nx,
                                    int ny, int pitch) {
     using C = Cross<Real, TY>;
     stage_lds<TY * C::RW, 8>(&s.row[0][0], [&](int i) {
         const int r = i / C::RW, c = i - r * C::RW;
         const int y = min(y0 + r, ny - 1);
         const int x = wrap(x0 - C::J + c, nx);
-        return phi[(long)y * pitch + x];
+        return (double)phi[(long)y * pitch + x];
     });
     stage_lds<C::CH * BX, 8>(&s.col[0][0], [&](int i) {
         const int r = i / BX, c = i - r * BX;
         const int y = wrap(y0 - C::J + r, ny);
         const int x = min(x0 + c, nx - 1);
-        return phi[(long)y * pitch + x];
+        return (double)phi[(long)y * pitch + x];
     });
 }
 
@@ -192,7 +196,8 @@ __global__ void __launch_bounds__(NT) k_collide(StepArgs<Real> a) {
     __shared__ Cross<Real, TY> s;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
-    stage_cross<Real, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    stage_cross<Real, TY>(s, static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in), x0, y0, a.nx, a.ny,
+                          pitch);
     __syncthreads();
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
@@ -240,7 +245,8 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
     __shared__ double red[4][NT / BX];
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
-    stage_cross<Real, TY>(s, a.phi_in, x0, y0, a.nx, a.ny, pitch);
+    stage_cross<Real, TY>(s, static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in), x0, y0, a.nx, a.ny,
+                          pitch);
     __syncthreads();
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
     double m = 0, px = 0, py = 0, vmax = 0;

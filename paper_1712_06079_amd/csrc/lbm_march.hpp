@@ -125,6 +125,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     // the many lane-dependent offsets out of the march would hold them in
     // registers for the whole kernel.  Only the wrapped lattice columns that
     // need a general modulo are kept (bcol, xcol, xring, xpair).
+    using P = typename PhiStore<Real, FORCE>::type;
+    const P* __restrict__ phin = static_cast<const P*>(a.phi_in);
+    P* __restrict__ phio = static_cast<P*>(a.phi_out);
     int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     int lane = tid & (BX - 1);
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
 #pragma unroll
         for (int j = 0; j < BPER; ++j) {
             const int i = min(tid + j * NT, TY * RW - 1);  // past the end: a duplicate, not stored
-            sbar.v[j] = a.phi_in[(long)wrapy(yn + 4 + i / RW) * pitch + bcol[j]];
+            sbar.v[j] = (double)phin[(long)wrapy(yn + 4 + i / RW) * pitch + bcol[j]];
         }
     };
     auto issue_fr = [&](int yn) {     // ring-cell populations of block yn
@@ -201,7 +204,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     };
     auto issue_col = [&](int yn) {    // rows NB blocks ahead of block yn (every lane; waves 2-3 unused)
 #pragma unroll
-        for (int j = 0; j < TY; ++j) pfar[j] = a.phi_in[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
+        for (int j = 0; j < TY; ++j) pfar[j] = (double)phin[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
     };
     // The interior populations and the new state are touched once per step:
     // non-temporal accesses keep them from evicting the potential rows, which
@@ -329,9 +332,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
     for (int j = 0; j < BP; ++j) {
         const int i = min(tid + j * NT, M::BAR_D - 1);  // past the end: a duplicate, not stored
         const int r = i / RW, c = i - r * RW;
-        vb[j] = a.phi_in[(long)wrapy(yb0 - 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
+        vb[j] = (double)phin[(long)wrapy(yb0 - 4 + r) * pitch + wrap(x0 - 1 - R + c, nx)];
     }
-    const double* colp = a.phi_in + xcol;  // this lane's column (waves 0-1)
+    const P* colp = phin + xcol;  // this lane's column (waves 0-1)
     double u[M::WARM_ROWS];
     if (colw) {
 #pragma unroll
@@ -624,15 +627,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                     moments(g[h], rho, jx, jy);
                     ph[h] = phi_of<FORCE>(potential(a.eos, rho));
                 }
-                double* pd = a.phi_out + (long)y * pitch + x;
+                P* pd = phio + (long)y * pitch + x;
                 if (VEC) {
-                    double __attribute__((ext_vector_type(2))) pv;
-                    pv.x = ph[0];
-                    pv.y = ph[1];
-                    __builtin_nontemporal_store(pv, reinterpret_cast<double __attribute__((ext_vector_type(2)))*>(pd));
+                    P __attribute__((ext_vector_type(2))) pv;
+                    pv.x = (P)ph[0];
+                    pv.y = (P)ph[1];
+                    __builtin_nontemporal_store(pv, reinterpret_cast<P __attribute__((ext_vector_type(2)))*>(pd));
                 } else {
-                    __builtin_nontemporal_store(ph[0], pd);
-                    if (x + 1 < nx) __builtin_nontemporal_store(ph[1], pd + 1);
+                    __builtin_nontemporal_store((P)ph[0], pd);
+                    if (x + 1 < nx) __builtin_nontemporal_store((P)ph[1], pd + 1);
                 }
             }
         }
