@@ -232,6 +232,23 @@ lbm_status lbm_adjoint_step(lbm_domain* d, const void* state_t, const double* la
 lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, int64_t nsteps, double* lam,
                              double* lam_tmp, double* grad, void* adj_ws, size_t adj_ws_bytes, hipStream_t stream);
 
+/* lbm_adjoint_step without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight loops, hosts
+ * that forbid allocation).  Same contract and result as lbm_adjoint_step; the
+ * scratch of its kernels is a fixed device array inside the library, one per
+ * GPU, of lbm_adjoint_noalloc_max_bytes() bytes (32 MiB: lattices up to about
+ * 1000 x 1000; the library's adjoint scratch is 4 FP64 planes of the padded
+ * lattice plus per-tile partials, lbm_adjoint_workspace_bytes).  LBM_EINVAL
+ * when the domain needs more.  Nothing is allocated and nothing needs
+ * clearing (every scratch word is written before it is read in a call).  All
+ * calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (different streams or threads) race and must be serialised by the caller. */
+lbm_status lbm_adjoint_step_noalloc(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t,
+                                    double* grad, hipStream_t stream);
+
+/* Size of the fixed scratch array of lbm_adjoint_step_noalloc (bytes). */
+size_t lbm_adjoint_noalloc_max_bytes(void);
+
 /* dJ/drho0 from dJ/df_0 for the initial state f_0 = f^eq(rho0, u0) of Eq. 2 at
  * fixed u0 (asynchronous): drho0 = sum_i lam0_i f^eq_i(1, u0).  lam0 device
  * FP64 [9][ny][nx]; ux0, uy0 device [ny][nx] or NULL (u0 = 0); drho0 device [ny][nx]. */

@@ -95,13 +95,17 @@ def library():
         L.lbm_record.argtypes = [_VP, C.c_int64, _VP, C.c_size_t, _VP]
         L.lbm_adjoint_steps.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
         L.lbm_stream_probe.argtypes = [C.c_int32, _VP, _VP, C.c_size_t, C.c_int32, _VP]
+        L.lbm_adjoint_step_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
+        L.lbm_adjoint_noalloc_max_bytes.argtypes = []
+        L.lbm_adjoint_noalloc_max_bytes.restype = C.c_size_t
         L.lbm_destroy.argtypes = [_VP]
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
                    "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
-                   "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps", "lbm_stream_probe"):
+                   "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps", "lbm_stream_probe",
+                   "lbm_adjoint_step_noalloc"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -283,6 +287,11 @@ class Domain:
         """lam = (d step / d f_t)^T lam_next at `state`; grad[0] += dJ/dg, grad[1] += dJ/dT."""
         check(library().lbm_adjoint_step(self._h, _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(grad), _ptr(adj_ws),
                                          adj_ws.numel(), _stream(stream)))
+
+    def adjoint_step_noalloc(self, state, lam_next, lam, grad, stream=None):
+        """adjoint_step with the library's fixed device scratch (lbm_adjoint_step_noalloc)."""
+        check(library().lbm_adjoint_step_noalloc(self._h, _ptr(state), _ptr(lam_next), _ptr(lam), _ptr(grad),
+                                                 _stream(stream)))
 
     def adjoint_rho0(self, lam0, ux0=None, uy0=None, stream=None):
         torch = _torch()

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/lbm.h"
@@ -640,6 +641,61 @@ lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, i
     }
     return LBM_OK;
 }
+
+}  // extern "C"
+
+namespace {
+// Scratch of lbm_adjoint_step_noalloc: one fixed array per device, resident
+// for the life of the process.  In host code `scratch` only names the symbol;
+// its device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the current device).
+lbm_status scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_EDEVICE, "device index %d beyond %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_EDEVICE, "scratch array address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_adjoint_step_noalloc(lbm_domain* d, const void* state_t, const double* lam_next, double* lam_t,
+                                    double* grad, hipStream_t stream) {
+    if (!d || !state_t || !lam_next || !lam_t || !grad) return fail(LBM_EINVAL, "NULL argument");
+    if (lam_next == lam_t) return fail(LBM_EINVAL, "lam_next and lam_t must be distinct buffers");
+    const size_t need = adj_layout(d).total;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(LBM_EINVAL, "lattice %d x %d needs %zu bytes of adjoint scratch, more than the %zu of the fixed array",
+                    d->p.nx, d->p.ny, need, NOALLOC_SCRATCH_BYTES);
+    void* ptr = nullptr;
+    lbm_status st = scratch_address(&ptr);
+    if (st != LBM_OK) return st;
+    st = adjoint_check(d, ptr, NOALLOC_SCRATCH_BYTES);
+    if (st != LBM_OK) return st;
+    char* w = static_cast<char*>(ptr);
+    st = adjoint_kernels(d, state_t, lam_next, lam_t, w, 0, stream);
+    if (st != LBM_OK) return st;
+    return adjoint_reduce(d, w, grad, stream);
+}
+
+size_t lbm_adjoint_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 lbm_status lbm_adjoint_rho0(lbm_domain* d, const double* lam0, const double* ux0, const double* uy0, double* drho0,
                             hipStream_t stream) {
