@@ -25,6 +25,8 @@
 //    c_s^2 = 1/3 (Sec. 2 after Eq. 6); dt = h = 1 (Sec. 2 after Eq. 1).
 //  * Eq. 20 carries no boundary closure: every grid line is periodic.  Its 2D
 //    use is dimension by dimension: d/dx along each row, d/dy along each column.
+//  * Eq. 15 as printed lacks the factor 1/c_s^2 = 3 (its sum is c_s^2 grad u);
+//    the factor is applied.
 //  * Eq. 29 (Carnahan-Starling) prints the denominator as (1 - (b rho/4)^3);
 //    the Carnahan-Starling form (1 - b rho/4)^3 is used.
 //  * Hu's scaling p_m = k p_EOS (Sec. 5) enters U = g (k p_EOS - rho c_s^2).
@@ -52,7 +54,8 @@ typedef struct {
     int32_t nx, ny;
     int32_t eos;    // 0 VDW (Eq. 24), 1 PR (Eq. 28), 2 CS (Eq. 29), 3 RK (Eq. 27), 4 RKS
     int32_t force;  // 0 Shan-Chen (Eq. 22), 1 Zhang-Chen (Eq. 7), 2 hybrid (Eq. 9)
-    int32_t grad;   // 0 high-order difference (Eq. 20), 1 central difference (Eq. 14)
+    int32_t grad;   // 0 high-order difference (Eq. 20), 1 central difference (Eq. 14),
+                    // 2 weighted D2Q9 central difference (Eq. 15, with the 1/c_s^2 factor)
     int32_t pad_;
     double tau;     // relaxation time (Eq. 1)
     double a, b, R, omega;  // EOS constants; omega = acentric factor (PR, RKS)
@@ -430,6 +433,43 @@ void derivative_line(int grad, int n, const S* u, long su, S* y, long sy) {
     else hdm_line<S>(n, u, su, y, sy);
 }
 
+// Weighted D2Q9 central difference, Eq. 15 of Sec. 3.1, periodic, with the
+// factor 1/c_s^2 = 3 that the printed sum lacks (sum_i w_i e_ix e_ix = 1/3,
+// so the printed sum is c_s^2 du/dx):
+//   du/dx(x) = 3 sum_i w_i u(x + e_i) e_ix,   du/dy(x) = 3 sum_i w_i u(x + e_i) e_iy.
+// axis 0 gives d/dx, axis 1 d/dy.
+template <typename S>
+void d2q9_derivative(int axis, int nx, int ny, const S* u, S* out) {
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            S acc(0.0);
+            for (int i = 1; i < 9; ++i) {
+                const int e = (axis == 0) ? EX[i] : EY[i];
+                const int xn = (x + EX[i] + nx) % nx, yn = (y + EY[i] + ny) % ny;
+                acc = acc + (3.0 * WQ[i] * e) * u[(size_t)yn * nx + xn];
+            }
+            out[(size_t)y * nx + x] = acc;
+        }
+    }
+}
+
+// d/dx (axis 0) or d/dy (axis 1) of the field u [ny][nx] with the gradient
+// scheme `grad`: 0 Eq. 20 and 1 Eq. 14, each along its own grid lines (d/dx
+// along every row, d/dy along every column); 2 the two-dimensional Eq. 15.
+template <typename S>
+void derivative(int grad, int axis, int nx, int ny, const S* u, S* out) {
+    if (grad == 2) {
+        d2q9_derivative<S>(axis, nx, ny, u, out);
+    } else if (axis == 0) {
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < ny; ++y) derivative_line<S>(grad, nx, &u[(size_t)y * nx], 1, &out[(size_t)y * nx], 1);
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int x = 0; x < nx; ++x) derivative_line<S>(grad, ny, &u[x], nx, &out[x], nx);
+    }
+}
+
 // ---------------------------------------------------------------- Eq. 2
 template <typename S>
 S feq(int i, S rho, S ux, S uy) {
@@ -489,16 +529,13 @@ void forces(const Model& m, const S* f, S T, S g, Work<S>& w) {
     }
     const bool need_phi = (m.p.force == 0 || m.p.force == 2);
     const bool need_U = (m.p.force == 1 || m.p.force == 2);
-    // d/dx along each row (fixed y), d/dy along each column (fixed x).
-#pragma omp parallel for schedule(static)
-    for (int y = 0; y < ny; ++y) {
-        if (need_phi) derivative_line<S>(m.p.grad, nx, &w.phi[(size_t)y * nx], 1, &w.gx[(size_t)y * nx], 1);
-        if (need_U) derivative_line<S>(m.p.grad, nx, &w.U[(size_t)y * nx], 1, &w.gux[(size_t)y * nx], 1);
+    if (need_phi) {
+        derivative<S>(m.p.grad, 0, nx, ny, w.phi.data(), w.gx.data());
+        derivative<S>(m.p.grad, 1, nx, ny, w.phi.data(), w.gy.data());
     }
-#pragma omp parallel for schedule(static)
-    for (int x = 0; x < nx; ++x) {
-        if (need_phi) derivative_line<S>(m.p.grad, ny, &w.phi[x], nx, &w.gy[x], nx);
-        if (need_U) derivative_line<S>(m.p.grad, ny, &w.U[x], nx, &w.guy[x], nx);
+    if (need_U) {
+        derivative<S>(m.p.grad, 0, nx, ny, w.U.data(), w.gux.data());
+        derivative<S>(m.p.grad, 1, nx, ny, w.U.data(), w.guy.data());
     }
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < (long)N; ++c) {
@@ -570,8 +607,9 @@ void step(const Model& m, const S* f, S* fout, S T, S g, Work<S>& w) {
 // and the step is f_{t+1,i}(x + e_i) = f*_i(x).  Given lam = dJ/df_{t+1}:
 //   mu_i(x) = lam_i(x + e_i)                                  (streaming)
 //   rho_bar, j_bar, F_bar from the partial derivatives of A    (collision)
-//   U_bar from F_bar through the force (D^T = -D: A is symmetric and B
-//        antisymmetric, both circulant, so A^-1 B is antisymmetric)
+//   U_bar from F_bar through the force (D^T = -D: for Eq. 20, A is symmetric
+//        and B antisymmetric, both circulant, so A^-1 B is antisymmetric; Eqs. 14
+//        and 15 have coefficients odd in the offset e_i)
 //   dJ/df_k(x) = (1 - 1/tau) mu_k + rho_bar + e_k.j_bar + U_bar dU/drho,
 // and the parameter gradients dJ/dg = sum U_bar dU/dg, dJ/dT = sum U_bar dU/dT.
 // dU/drho, dU/dg and dU/dT come from the dual-number evaluation of U.
@@ -629,8 +667,8 @@ void adjoint_step(const Model& m, const double* f, const double* lam_next, doubl
             ax[c] = -2.0 * s * w.phi[c] * wsc * Fbx[c];
             ay[c] = -2.0 * s * w.phi[c] * wsc * Fby[c];
         }
-        for (int y = 0; y < ny; ++y) derivative_line<double>(m.p.grad, nx, &ax[(size_t)y * nx], 1, &dax[(size_t)y * nx], 1);
-        for (int x = 0; x < nx; ++x) derivative_line<double>(m.p.grad, ny, &ay[x], nx, &day[x], nx);
+        derivative<double>(m.p.grad, 0, nx, ny, ax.data(), dax.data());
+        derivative<double>(m.p.grad, 1, nx, ny, ay.data(), day.data());
         for (size_t c = 0; c < N; ++c) {
             double s = (w.U[c] >= 0.0) ? 1.0 : -1.0;
             double phibar = -2.0 * s * wsc * (Fbx[c] * w.gx[c] + Fby[c] * w.gy[c]) - dax[c] - day[c];
@@ -641,8 +679,8 @@ void adjoint_step(const Model& m, const double* f, const double* lam_next, doubl
     if (zc) {
         // F = -(D_x U, D_y U):  U_bar = -D^T F_bar = D_x F_bar_x + D_y F_bar_y
         for (size_t c = 0; c < N; ++c) { ax[c] = wzc * Fbx[c]; ay[c] = wzc * Fby[c]; }
-        for (int y = 0; y < ny; ++y) derivative_line<double>(m.p.grad, nx, &ax[(size_t)y * nx], 1, &dax[(size_t)y * nx], 1);
-        for (int x = 0; x < nx; ++x) derivative_line<double>(m.p.grad, ny, &ay[x], nx, &day[x], nx);
+        derivative<double>(m.p.grad, 0, nx, ny, ax.data(), dax.data());
+        derivative<double>(m.p.grad, 1, nx, ny, ay.data(), day.data());
         for (size_t c = 0; c < N; ++c) Ubar[c] += dax[c] + day[c];
     }
     // U = g (k p(rho, T) - rho/3): chain into rho and the parameters
@@ -695,6 +733,13 @@ void orc_eos(const orc_params* p, double rho, double T, double* pe, double* dp, 
 }
 
 void orc_hdm_line(int n, const double* u, double* du) { hdm_line<double>(n, u, 1, du, 1); }
+
+// Both derivatives of a field u [ny][nx] with the scheme p->grad (the step's
+// gradient operator, Sec. 3): gx = d/dx, gy = d/dy.
+void orc_gradient(const orc_params* p, const double* u, double* gx, double* gy) {
+    derivative<double>(p->grad, 0, p->nx, p->ny, u, gx);
+    derivative<double>(p->grad, 1, p->nx, p->ny, u, gy);
+}
 void orc_cdm_line(int n, const double* u, double* du) { cdm_line<double>(n, u, 1, du, 1); }
 
 void orc_feq(double rho, double ux, double uy, double* out9) {

@@ -13,7 +13,7 @@ from . import build as _build
 
 EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
 FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
-GRAD = {"hdm": 0, "cdm": 1}
+GRAD = {"hdm": 0, "cdm": 1, "cdm9": 2}
 
 EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
 EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
@@ -60,6 +60,7 @@ def load(path: str):
     L.orc_eos.argtypes = [P, C.c_double, C.c_double, _D, _D, _D]
     L.orc_hdm_line.argtypes = [C.c_int, _D, _D]
     L.orc_cdm_line.argtypes = [C.c_int, _D, _D]
+    L.orc_gradient.argtypes = [P, _D, _D, _D]
     L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, _D]
     L.orc_collide_cell.argtypes = [_D, C.c_double, C.c_double, C.c_double, _D]
     L.orc_init.argtypes = [P, _D, _D, _D, _D]
@@ -139,6 +140,15 @@ def cdm_line(u):
     out = np.empty_like(u)
     lib().orc_cdm_line(len(u), _ptr(u), _ptr(out))
     return out
+
+
+def gradient(p: Params, u):
+    """(d/dx, d/dy) of a field u [ny, nx] with the step's gradient scheme p.grad."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.shape == (p.ny, p.nx)
+    gx, gy = np.empty_like(u), np.empty_like(u)
+    lib().orc_gradient(C.byref(p.c()), _ptr(u), _ptr(gx), _ptr(gy))
+    return gx, gy
 
 
 def feq(rho, ux, uy):

@@ -118,6 +118,54 @@ def pin_cdm_wavenumber():
         assert np.max(np.abs(du - np.sin(th) * np.cos(th * j))) < 2e-14
 
 
+def _mode(nx, ny, mx, my, phase=0.4):
+    tx, ty = 2 * np.pi * mx / nx, 2 * np.pi * my / ny
+    y, x = np.mgrid[0:ny, 0:nx]
+    arg = tx * x + ty * y + phase
+    return tx, ty, np.sin(arg), np.cos(arg)
+
+
+def pin_d2q9_symbol():
+    """Eq. 15 with the 1/c_s^2 factor on a 2D Fourier mode u = sin(theta.x + c):
+    the four axis neighbours give (2/3) sin(theta_x) and the four diagonals
+    (1/3) sin(theta_x) cos(theta_y), so d/dx u = [(2/3) sin tx + (1/3) sin tx
+    cos ty] cos(theta.x + c), and d/dy the same with x and y exchanged."""
+    p = O.Params(nx=12, ny=10, grad="cdm9")
+    for mx in range(12):
+        for my in range(10):
+            tx, ty, u, c = _mode(12, 10, mx, my)
+            gx, gy = O.gradient(p, u)
+            kx = (2 / 3) * np.sin(tx) + (1 / 3) * np.sin(tx) * np.cos(ty)
+            ky = (2 / 3) * np.sin(ty) + (1 / 3) * np.sin(ty) * np.cos(tx)
+            assert np.max(np.abs(gx - kx * c)) < 5e-14 and np.max(np.abs(gy - ky * c)) < 5e-14, (mx, my)
+
+
+def pin_d2q9_flat_equals_eq14():
+    """On a field that varies along x only, Eq. 15 is Eq. 14: the diagonal
+    pairs repeat the axis difference, (1/3 + 2/12)(u_{x+1} - u_{x-1}); and
+    d/dy vanishes (every term cancels a term of equal value: zero up to the
+    rounding of the partial sums)."""
+    rng = np.random.default_rng(12)
+    prof = rng.standard_normal(17)
+    u = np.repeat(prof[None, :], 6, axis=0)
+    gx, gy = O.gradient(O.Params(nx=17, ny=6, grad="cdm9"), u)
+    assert np.max(np.abs(gy)) < 4e-16 * np.abs(prof).max()
+    assert np.max(np.abs(gx - O.cdm_line(prof)[None, :])) < 4e-16 * np.abs(prof).max()
+
+
+def pin_gradient_per_axis():
+    """The 2D use of Eq. 20 is dimension by dimension: on a 2D mode d/dx has
+    the one-dimensional symbol k'(theta_x) of Eq. 20 whatever theta_y is
+    (and Eq. 14 has sin theta_x)."""
+    for grad, sym in (("hdm", hdm_symbol), ("cdm", np.sin)):
+        p = O.Params(nx=11, ny=8, grad=grad)
+        for mx, my in ((1, 0), (2, 3), (5, 1), (3, 4)):
+            tx, ty, u, c = _mode(11, 8, mx, my)
+            gx, gy = O.gradient(p, u)
+            assert np.max(np.abs(gx - sym(tx) * c)) < 1e-14, (grad, mx, my)
+            assert np.max(np.abs(gy - sym(ty) * c)) < 1e-14, (grad, mx, my)
+
+
 def pin_tanh_profile_errors():
     """Sec. 3 / Figs. 1-3 (Eqs. 16-18): on rho = 1 + tanh(2x/W) the HDM error is far
     below the CDM error and both fall as W grows.  The profile is made periodic
@@ -522,7 +570,8 @@ def pin_adjoint_dot_product():
     the two are derived independently, so agreement to rounding pins both."""
     rng = np.random.default_rng(21)
     for eos, force, grad in (("cs", "sc", "hdm"), ("vdw", "zc", "hdm"), ("pr", "sc", "hdm"), ("rks", "hybrid", "hdm"),
-                             ("rk", "zc", "cdm"), ("vdw", "sc", "cdm")):
+                             ("rk", "zc", "cdm"), ("vdw", "sc", "cdm"), ("cs", "sc", "cdm9"), ("pr", "zc", "cdm9"),
+                             ("vdw", "hybrid", "cdm9")):
         p, f, _, _, _ = _adjoint_case(eos, force, grad)
         lam = rng.standard_normal(f.shape)
         df = rng.standard_normal(f.shape) * 1e-2 * f
@@ -605,7 +654,7 @@ def pin_table1_laplace():
 
 FAST = [
     pin_hdm_modified_wavenumber, pin_hdm_dense_solve, pin_hdm_sixth_order, pin_hdm_antisymmetric,
-    pin_cdm_wavenumber, pin_tanh_profile_errors, pin_eos_derivatives, pin_critical_points,
+    pin_cdm_wavenumber, pin_d2q9_symbol, pin_d2q9_flat_equals_eq14, pin_gradient_per_axis, pin_tanh_profile_errors, pin_eos_derivatives, pin_critical_points,
     pin_pr_alpha_at_tc, pin_acentric_factor, pin_maxwell_vdw_table, pin_maxwell_near_critical, pin_equilibrium_moments,
     pin_edm_collision, pin_streaming_shift, pin_mass_momentum_conservation, pin_uniform_fixed_point,
     pin_x_invariance, pin_shift_equivariance, pin_mirror_symmetry, pin_shear_wave_viscosity,

@@ -69,6 +69,12 @@ MUTANTS = {
                            "lam[k * N + c] = (1.0 - 1.0 / tau) * mu[k] + rb + EX[k] * jbx_ + EX[k] * jby_;"),
     "adjoint_dA_dm": ("*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 3.0 * mx) / rho);", "*dmx = WQ[i] * (3.0 * EX[i] + (9.0 * em * EX[i] - 1.5 * mx) / rho);"),
     "dp_drho_cs": ("return R * T * (Z + e * Zp) - 2.0 * a * rho;", "return R * T * (Z + Zp) - 2.0 * a * rho;"),
+    "d2q9_without_cs2_factor": ("acc = acc + (3.0 * WQ[i] * e) * u[(size_t)yn * nx + xn];",
+                                "acc = acc + (WQ[i] * e) * u[(size_t)yn * nx + xn];"),
+    "d2q9_axis_swapped": ("const int e = (axis == 0) ? EX[i] : EY[i];", "const int e = (axis == 0) ? EY[i] : EX[i];"),
+    "d2q9_dropped_diagonals": ("for (int i = 1; i < 9; ++i) {\n                const int e", "for (int i = 1; i < 5; ++i) {\n                const int e"),
+    "d2q9_neighbour_index": ("const int xn = (x + EX[i] + nx) % nx, yn = (y + EY[i] + ny) % ny;",
+                             "const int xn = (x + EX[i] + nx) % nx, yn = (y - EY[i] + ny) % ny;"),
     # Eq. 9 weights, changed consistently in the forward force and its adjoint
     # (a mistake made in both passes survives the dot-product identity)
     "hybrid_sc_weight_both_passes": ("(1.0 - 2.0 * m.p.A)", "(1.0 - m.p.A)"),
