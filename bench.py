@@ -174,14 +174,40 @@ def stream_model(kernel: str, name: str, prec: str, probe, launch_ms: float):
             "write_GBps": probe["write"]["GBps"], "model_ms": round(ms, 5), "frac_of_model": round(ms / launch_ms, 4)}
 
 
-def batch_sweep(steps: int, sep_steps: int, seed: int = 2024):
+def _bulk(rho, nx):
+    """Bulk densities of an x-slab (liquid in the middle half): the mean of the
+    central N_x/8 columns and of the N_x/8 columns around x = 0."""
+    w = max(nx // 8, 1)
+    rl = rho[nx // 2 - w // 2:nx // 2 - w // 2 + w].mean()
+    rv = np.concatenate([rho[:w // 2 + 1], rho[nx - w // 2:]]).mean()
+    return float(rl), float(rv)
+
+
+def _coexistence(b, ps, maxw):
+    """Per-domain relative errors of the bulk densities against the Maxwell
+    rule (None for a domain holding a non-finite density)."""
+    flags = b.check_finite()
+    out = []
+    for i, p in enumerate(ps):
+        if flags[i]:
+            out.append(None)
+            continue
+        rho = b.domain(i).moments(want=("rho",))["rho"].mean(dim=0).cpu().numpy()
+        rl, rv = _bulk(rho, p.nx)
+        out.append((rl / maxw[i][1] - 1, rv / maxw[i][0] - 1))
+    return out
+
+
+def batch_sweep(steps: int, sep_steps: int, seed: int = 2024, settle_steps: int = 40000):
     """The coexistence sweep: 64 periodic flat-interface domains, N_x in
     {128, 256, 512}, N_y in {8, 16, 32} from the seed, 32 Peng-Robinson
     (a = 2/49, b = 2/21, omega = 0.344) and 32 Carnahan-Starling (a = 1, b = 4),
     k = 0.04, T_r = linspace(0.5, 0.95, 32) per group, tau = 1, SC + HDM, FP64,
     x-slab of the Maxwell densities (W = 5) with noise 1e-4.  Times the batched
     graph-replayed launch against one fused launch per domain per step, then
-    compares the bulk densities with the Maxwell rule."""
+    compares every domain's bulk densities with the Maxwell rule after the
+    timed steps and again after `settle_steps` more (their change shows whether
+    a domain has settled)."""
     import torch
 
     import paper_1712_06079_amd as L
@@ -216,29 +242,92 @@ def batch_sweep(steps: int, sep_steps: int, seed: int = 2024):
     torch.cuda.synchronize()
     ms_sep = e[0].elapsed_time(e[1]) / sep_steps
     ms_bat = e[2].elapsed_time(e[3]) / steps
-    flags = b.check_finite()
-    errs = []
+    errs = _coexistence(b, ps, maxw)
+    if settle_steps > 0:
+        b.step(settle_steps)
+        errs2 = _coexistence(b, ps, maxw)
+    else:
+        errs2 = errs
+    doms = []
     for i, p in enumerate(ps):
-        if flags[i]:
-            errs.append(None)
-            continue
-        rho = b.domain(i).moments(want=("rho",))["rho"].mean(dim=0).cpu().numpy()
-        w = max(p.nx // 8, 1)
-        rl = rho[p.nx // 2 - w // 2:p.nx // 2 - w // 2 + w].mean()
-        rv = np.concatenate([rho[:w // 2 + 1], rho[p.nx - w // 2:]]).mean()
-        errs.append((abs(rl / maxw[i][1] - 1), abs(rv / maxw[i][0] - 1)))
+        a, c = errs[i], errs2[i]
+        doms.append({"eos": p.eos, "T_r": round(float(trs[i % 32]), 4), "nx": p.nx, "ny": p.ny,
+                     "rho_v_maxwell": maxw[i][0], "rho_l_maxwell": maxw[i][1],
+                     "err_l": None if a is None else round(a[0], 6), "err_v": None if a is None else round(a[1], 5),
+                     f"err_l_{steps + 16 + settle_steps}": None if c is None else round(c[0], 6),
+                     f"err_v_{steps + 16 + settle_steps}": None if c is None else round(c[1], 5)})
     ok = [x for x in errs if x is not None]
+    hot = [x for x, i in zip(errs2, range(64)) if x is not None and trs[i % 32] >= 0.6]
     return {
         "domains": 64, "cells": cells, "steps": steps, "ms_per_step_batched": round(ms_bat, 5),
         "ms_per_step_separate": round(ms_sep, 5), "domain_steps_per_s": round(64 / (ms_bat * 1e-3), 1),
         "domain_steps_per_s_separate": round(64 / (ms_sep * 1e-3), 1), "speedup": round(ms_sep / ms_bat, 2),
         "mlups_batched": round(cells / (ms_bat * 1e-3) / 1e6, 1), "schedule": tune.get("best"),
-        "nonfinite_domains": int(sum(flags)),
-        "maxwell_rel_err_liquid_max": round(max(x[0] for x in ok), 5) if ok else None,
-        "maxwell_rel_err_vapour_max": round(max(x[1] for x in ok), 5) if ok else None,
-        "maxwell_rel_err_liquid_median": round(float(np.median([x[0] for x in ok])), 5) if ok else None,
-        "maxwell_rel_err_vapour_median": round(float(np.median([x[1] for x in ok])), 5) if ok else None,
+        "nonfinite_domains": int(sum(x is None for x in errs)),
+        "maxwell_rel_err_liquid_max": round(max(abs(x[0]) for x in ok), 5) if ok else None,
+        "maxwell_rel_err_vapour_max": round(max(abs(x[1]) for x in ok), 5) if ok else None,
+        "maxwell_rel_err_liquid_median": round(float(np.median([abs(x[0]) for x in ok])), 5) if ok else None,
+        "maxwell_rel_err_vapour_median": round(float(np.median([abs(x[1]) for x in ok])), 5) if ok else None,
+        "settled_after_steps": steps + 16 + settle_steps,
+        "settled_T_r_ge_0.6_liquid_max": round(max(abs(x[0]) for x in hot), 5) if hot else None,
+        "settled_T_r_ge_0.6_vapour_max": round(max(abs(x[1]) for x in hot), 5) if hot else None,
+        "per_domain": doms,
     }
+
+
+FIG5_EOS = {"vdw": dict(a=9 / 49, b=2 / 21, k=0.01), "rk": dict(a=9 / 49, b=2 / 21, k=0.02),
+            "pr": dict(a=9 / 49, b=2 / 21, k=0.04, omega=0.344), "cs": dict(a=1.0, b=4.0, k=0.04)}
+FIG5_TR = (0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95)
+FIG5_HYBRID_A = -0.3
+
+
+def fig5_coexistence(steps: int = 60000, nx: int = 256, ny: int = 8):
+    """Coexistence densities against the Maxwell rule for the four EOS of the
+    coexistence study (van der Waals k = 0.01, Redlich-Kwong k = 0.02, PR water
+    k = 0.04, Carnahan-Starling k = 0.04; a = 9/49, b = 2/21 except CS a = 1,
+    b = 4), tau = 1.6, flat interface (x-slab, W = 5) on a periodic nx x ny
+    lattice, T_r = 0.55 .. 0.95, for Shan-Chen and Zhang-Chen with the
+    high-order difference (Eq. 20) and with the weighted central difference
+    (Eq. 15), and the hybrid force (Eq. 9) with Eq. 15 at A = -0.3 and
+    g = 1/(1 - A) (the weights of Eq. 9 as printed sum to 1 - A).  One batched
+    run per variant; per-domain relative errors of the bulk densities."""
+    import paper_1712_06079_amd as L
+    import torch
+    variants = [("sc", "hdm", 0.0), ("zc", "hdm", 0.0), ("sc", "cdm9", 0.0), ("zc", "cdm9", 0.0),
+                ("hybrid", "cdm9", FIG5_HYBRID_A)]
+    out = {"steps": steps, "lattice": [nx, ny], "tau": 1.6, "variants": {}}
+    for force, grad, A in variants:
+        ps, rhos, maxw, lab = [], [], [], []
+        for eos, c in FIG5_EOS.items():
+            for tr in FIG5_TR:
+                p = L.Params(nx=nx, ny=ny, eos=eos, force=force, grad=grad, R=1.0, tau=1.6, A=A,
+                             g=1.0 / (1.0 - A) if force == "hybrid" else 1.0, **c)
+                tc, _ = L.critical(p)
+                p.T = tr * tc
+                rv, rl, _ = L.maxwell(p, p.T)
+                ps.append(p)
+                maxw.append((rv, rl))
+                lab.append((eos, tr))
+                rhos.append(torch.from_numpy(I.slab(nx, ny, rv, rl, 5.0, axis="x", noise=1e-4 * rv, seed=7)).cuda())
+        b = L.Batch(ps, rhos)
+        b.step(steps)
+        errs = _coexistence(b, ps, maxw)
+        key = f"{force}_{grad}" + (f"_A{A}" if force == "hybrid" else "")
+        rows = {}
+        for (eos, tr), e in zip(lab, errs):
+            rows.setdefault(eos, []).append({"T_r": tr, "err_l": None if e is None else round(e[0], 6),
+                                             "err_v": None if e is None else round(e[1], 5)})
+        fin = [e for e in errs if e is not None]
+        hot = [e for e, (_, tr) in zip(errs, lab) if e is not None and tr >= 0.7]
+        out["variants"][key] = {
+            "per_eos": rows, "nonfinite": int(sum(e is None for e in errs)),
+            "max_abs_err_l": round(max(abs(e[0]) for e in fin), 5) if fin else None,
+            "max_abs_err_v_T_r_ge_0.7": round(max(abs(e[1]) for e in hot), 5) if hot else None}
+        print(f"[bench] fig5 {key}: non-finite {out['variants'][key]['nonfinite']}, liquid max "
+              f"{out['variants'][key]['max_abs_err_l']}, vapour max (T_r >= 0.7) "
+              f"{out['variants'][key]['max_abs_err_v_T_r_ge_0.7']}", file=sys.stderr, flush=True)
+        del b
+    return out
 
 
 def adjoint_cost(steps: int, every: int, seed: int = 2024):
@@ -638,6 +727,7 @@ def main():
                     help="steps timed right after the headline window on the same domain (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
+    ap.add_argument("--fig5-steps", type=int, default=60000, help="steps of the coexistence comparison (0 = skip)")
     ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
     ap.add_argument("--long-steps", type=int, default=50000, help="FP32-vs-FP64 large-case steps (0 = skip)")
     ap.add_argument("--curve-steps", type=int, default=200, help="steps per point of the size curve (0 = skip)")
@@ -686,6 +776,7 @@ def main():
         batch = batch_sweep(args.batch_steps, max(args.batch_steps // 10, 20))
         print(f"[bench] batch: {batch['domain_steps_per_s']:.0f} domain-steps/s batched, "
               f"{batch['domain_steps_per_s_separate']:.0f} separate", file=sys.stderr, flush=True)
+    fig5 = fig5_coexistence(args.fig5_steps) if args.fig5_steps > 0 else None
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_cost(args.adjoint_steps, 70)
@@ -723,6 +814,8 @@ def main():
         line["other_precision"] = other
     if batch:
         line["batch"] = batch
+    if fig5:
+        line["fig5_coexistence"] = fig5
     if adjoint:
         line["adjoint"] = adjoint
     if droplet:

@@ -55,7 +55,7 @@ typedef enum {
 
 typedef enum { LBM_EOS_VDW = 0, LBM_EOS_PR = 1, LBM_EOS_CS = 2, LBM_EOS_RK = 3, LBM_EOS_RKS = 4 } lbm_eos;
 typedef enum { LBM_FORCE_SC = 0, LBM_FORCE_ZC = 1, LBM_FORCE_HYBRID = 2 } lbm_force;
-typedef enum { LBM_GRAD_HDM = 0, LBM_GRAD_CDM = 1 } lbm_grad;
+typedef enum { LBM_GRAD_HDM = 0, LBM_GRAD_CDM = 1, LBM_GRAD_CDM9 = 2 } lbm_grad;
 typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
 
 /* Problem statement of one periodic domain (Secs. 2, 4, 5.2).
@@ -64,7 +64,9 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
  *          the Carnahan-Starling denominator (1 - b rho/4)^3), RK (Eq. 27,
  *          alpha = 1/sqrt(T)), RKS (Eq. 27 with the Soave alpha(T_r))
  *  force   Shan-Chen (Eq. 22), Zhang-Chen (Eq. 7), hybrid (Eq. 9, weight A)
- *  grad    HDM (Eq. 20) or central difference (Eq. 14)
+ *  grad    HDM (Eq. 20), central difference along each axis (Eq. 14) or the
+ *          weighted D2Q9 central difference (Eq. 15, with the factor
+ *          1/c_s^2 = 3 that the printed sum lacks)
  *  prec    storage precision of the populations (FP64 or FP32); all arithmetic
  *          is FP64.  The potential field is stored in FP64, except with FP32
  *          populations and the Shan-Chen or Zhang-Chen force, where it is
@@ -259,7 +261,9 @@ lbm_status lbm_adjoint_rho0(lbm_domain* d, const double* lam0, const double* ux0
 
 /* Many independent periodic domains that differ in size, EOS, temperature
  * and constants (the coexistence-curve sweep of Sec. 5.2, Fig. 5) but share
- * precision and force, advanced together: one launch per step of a worklist
+ * precision and force (and either all or none use the Eq. 15 gradient; the
+ * hybrid weight A and the other gradients may differ), advanced together: one
+ * launch per step of a worklist
  * kernel whose tiles cover every domain, replayed from a captured hipGraph.
  * A scheduler setting (tile height, worklist order, workgroups of the
  * persistent launch) is picked by lbm_batch_autotune. */
@@ -271,7 +275,9 @@ lbm_status lbm_batch_workspace_bytes(const lbm_params* params, int32_t n, size_t
 /* Create a batch in `workspace` (device, 256-byte aligned, caller-owned, kept
  * until lbm_batch_destroy) with domain i = params[i] initialised to
  * f^eq(rho0s[i], 0) (Eq. 2).  rho0s is a host array of n device pointers to
- * FP64 fields [ny_i][nx_i].  Validates like lbm_init; synchronises `stream`. */
+ * FP64 fields [ny_i][nx_i].  Validates like lbm_init (LBM_EINVAL also when
+ * the domains differ in precision, force or use of Eq. 15); synchronises
+ * `stream`. */
 lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace, size_t workspace_bytes,
                             const double* const* rho0s, hipStream_t stream, lbm_batch** out);
 
@@ -291,8 +297,11 @@ lbm_domain* lbm_batch_domain(lbm_batch* b, int32_t i);
 
 /* Scheduler setting: tile_y rows per tile (4 or 8), order (0 = domain order,
  * 1 = largest domains first, 2 = round robin over domains), grid = workgroups
- * of the persistent launch (0 = one per tile).  set synchronises the null stream. */
-lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid);
+ * of the persistent launch (0 = one per tile).  set copies the new worklist on
+ * `stream` and synchronises it: batched steps queued on `stream` before the
+ * call finish with the old schedule.  Steps queued on other streams must be
+ * complete (the caller synchronises them).  LBM_EINVAL for other values. */
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid, hipStream_t stream);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* order, int32_t* grid);
 
 /* Time every scheduler candidate over probe_steps batched steps with HIP

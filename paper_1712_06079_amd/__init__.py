@@ -17,7 +17,7 @@ __all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxw
 
 EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
 FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
-GRAD = {"hdm": 0, "cdm": 1}
+GRAD = {"hdm": 0, "cdm": 1, "cdm9": 2}
 PREC = {"f64": 0, "f32": 1}
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_hip.so")
 
@@ -334,7 +334,7 @@ class Batch:
         L.lbm_batch_step_separate.argtypes = [_VP, C.c_int64, _VP]
         L.lbm_batch_domain.argtypes = [_VP, C.c_int32]
         L.lbm_batch_domain.restype = _VP
-        L.lbm_batch_set_schedule.argtypes = [_VP, C.c_int32, C.c_int32, C.c_int32]
+        L.lbm_batch_set_schedule.argtypes = [_VP, C.c_int32, C.c_int32, C.c_int32, _VP]
         L.lbm_batch_get_schedule.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.lbm_batch_autotune.argtypes = [_VP, C.c_int32, _VP, C.c_char_p, C.c_size_t]
         L.lbm_batch_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
@@ -388,8 +388,8 @@ class Batch:
             raise IndexError(i)
         return _DomainView(self, C.c_void_p(h), self.params[i])
 
-    def set_schedule(self, tile_y: int, order: int, grid: int):
-        check(self._sigs().lbm_batch_set_schedule(self._h, tile_y, order, grid))
+    def set_schedule(self, tile_y: int, order: int, grid: int, stream=None):
+        check(self._sigs().lbm_batch_set_schedule(self._h, tile_y, order, grid, _stream(stream)))
 
     def schedule(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

@@ -53,7 +53,7 @@ lbm_status validate(const lbm_params* p) {
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau = %g must be > 1/2", p->tau);
     if (p->eos < 0 || p->eos > 4) return fail(LBM_EINVAL, "unknown eos %d", p->eos);
     if (p->force < 0 || p->force > 2) return fail(LBM_EINVAL, "unknown force %d", p->force);
-    if (p->grad < 0 || p->grad > 1) return fail(LBM_EINVAL, "unknown gradient %d", p->grad);
+    if (p->grad < 0 || p->grad > 2) return fail(LBM_EINVAL, "unknown gradient %d", p->grad);
     if (p->prec < 0 || p->prec > 1) return fail(LBM_EINVAL, "unknown precision %d", p->prec);
     if (!(p->a > 0) || !(p->b > 0) || !(p->R > 0)) return fail(LBM_EINVAL, "EOS constants a, b, R must be > 0");
     if (!(p->T > 0) || !std::isfinite(p->T)) return fail(LBM_EINVAL, "T = %g must be > 0", p->T);
@@ -307,7 +307,7 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
     d->off_part = 2 * L.f + 2 * L.phi;
     d->off_scr = d->off_part + L.part;
     const int radius = p->prec == LBM_F32 ? lbm::Radius<float>::value : lbm::Radius<double>::value;
-    if (p->grad == LBM_GRAD_CDM) {
+    if (p->grad == LBM_GRAD_CDM || p->grad == LBM_GRAD_CDM9) {  // (Eq. 15 kernels take their own path)
         d->tx = d->ty = 1;
         lbm_host::cdm_row(1, d->dx);
         lbm_host::cdm_row(1, d->dy);
@@ -583,6 +583,7 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
 lbm_status adjoint_check(lbm_domain* d, const void* adj_ws, size_t adj_ws_bytes) {
     if (d->p.prec != LBM_F64) return fail(LBM_EUNSUPPORTED, "the adjoint step is implemented for FP64 domains");
     if (d->p.force == LBM_FORCE_HYBRID) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the SC and ZC forces");
+    if (d->p.grad == LBM_GRAD_CDM9) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the Eq. 20 and Eq. 14 gradients");
     if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
     AdjLayout L = adj_layout(d);
     if (adj_ws_bytes < L.total) return fail(LBM_ENOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);

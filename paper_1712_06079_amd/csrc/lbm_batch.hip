@@ -20,7 +20,7 @@ using namespace lbm_internal;
 
 struct lbm_batch {
     int n;
-    int prec, force;
+    int prec, force, grad9;
     std::vector<lbm_domain*> doms;
     std::vector<size_t> dom_off, dom_bytes;
     char* ws;
@@ -88,7 +88,12 @@ void launch_batch_t(const lbm_batch* b, int parity, hipStream_t s) {
     const auto* descs = reinterpret_cast<const lbm::StepArgs<Real>*>(b->ws + b->off_desc[parity]);
     const auto* tiles = reinterpret_cast<const lbm::BatchTile*>(b->ws + b->off_tiles);
     const int grid = b->grid > 0 ? std::min(b->grid, b->ntiles) : b->ntiles;
-    hipLaunchKernelGGL((lbm::k_batch<Real, FORCE, TY, RY>), dim3(grid), dim3(lbm::NT), 0, s, descs, tiles, b->ntiles);
+    if (b->grad9)
+        hipLaunchKernelGGL((lbm::k_batch<Real, FORCE, TY, 16, true>), dim3(grid), dim3(lbm::NT), 0, s, descs, tiles,
+                           b->ntiles);
+    else
+        hipLaunchKernelGGL((lbm::k_batch<Real, FORCE, TY, RY>), dim3(grid), dim3(lbm::NT), 0, s, descs, tiles,
+                           b->ntiles);
 }
 
 template <typename Real, int FORCE>
@@ -123,6 +128,9 @@ void set_parity(lbm_batch* b, int cur) {
     for (auto* d : b->doms) d->cur = cur;
 }
 
+// Replace the worklist (copied on stream s, which is then synchronised, so
+// launches queued on s before the call have read the old list) and drop the
+// captured graph.
 lbm_status upload_tiles(lbm_batch* b, hipStream_t s) {
     std::vector<lbm::BatchTile> t = make_tiles(b, b->tile_y, b->order);
     if (t.size() > b->tiles_cap) return fail(LBM_EINVAL, "tile list exceeds its workspace area");
@@ -195,8 +203,9 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace
     if (!params || !workspace || !rho0s || !out || n < 1) return fail(LBM_EINVAL, "invalid batch arguments");
     if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
     for (int i = 1; i < n; ++i)
-        if (params[i].prec != params[0].prec || params[i].force != params[0].force)
-            return fail(LBM_EINVAL, "all domains of a batch share precision and force");
+        if (params[i].prec != params[0].prec || params[i].force != params[0].force ||
+            (params[i].grad == LBM_GRAD_CDM9) != (params[0].grad == LBM_GRAD_CDM9))
+            return fail(LBM_EINVAL, "all domains of a batch share precision, force and (Eq. 15 or not) gradient");
     BatchLayout L;
     lbm_status st = batch_layout(params, n, &L);
     if (st != LBM_OK) return st;
@@ -206,6 +215,7 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* workspace
     b->n = n;
     b->prec = params[0].prec;
     b->force = params[0].force;
+    b->grad9 = params[0].grad == LBM_GRAD_CDM9 ? 1 : 0;
     b->ws = static_cast<char*>(workspace);
     b->ws_bytes = workspace_bytes;
     size_t pos = L.off.empty() ? 0 : L.off[n - 1] + align256(L.bytes[n - 1]);
@@ -318,14 +328,17 @@ lbm_domain* lbm_batch_domain(lbm_batch* b, int32_t i) {
     return b->doms[i];
 }
 
-lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid) {
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid, hipStream_t stream) {
     if (!b) return fail(LBM_EINVAL, "NULL batch");
     if ((tile_y != 4 && tile_y != 8) || order < 0 || order > 2 || grid < 0)
         return fail(LBM_EINVAL, "schedule tile_y %d, order %d, grid %d", tile_y, order, grid);
     b->tile_y = tile_y;
     b->order = order;
     b->grid = grid;
-    return upload_tiles(b, nullptr);
+    // the new worklist is copied on `stream`, behind every launch already
+    // queued there, and the stream is synchronised before the graph that
+    // reads the old worklist is destroyed
+    return upload_tiles(b, stream);
 }
 
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* order, int32_t* grid) {

@@ -190,6 +190,19 @@ struct StepArgs {
     // it to rounding): rec_x / rec_y select it per axis; rK = C / (1 - r).
     int rec_x, rec_y;
     double rr, rr3, rr4, rd1, rd2, rK;
+    // 1: the gradient is the weighted D2Q9 difference of Eq. 15 (with the
+    // 1/c_s^2 factor) instead of a per-axis stencil.
+    int grad9;
 };
+
+// Eq. 15 with the factor 1/c_s^2 = 3 at the centre of a 3 x 3 neighbourhood
+// (m: row y-1, c: row y, p: row y+1; index 0, 1, 2 = x-1, x, x+1):
+//   d/dx = (1/3)(c2 - c0) + (1/12)[(p2 - p0) + (m2 - m0)],
+//   d/dy = (1/3)(p1 - m1) + (1/12)[(p2 - m2) + (p0 - m0)].
+__device__ inline void grad_d2q9(const double* m, const double* c, const double* p, double& gx, double& gy) {
+    const double a = 1.0 / 3.0, d = 1.0 / 12.0;
+    gx = a * (c[2] - c[0]) + d * ((p[2] - p[0]) + (m[2] - m[0]));
+    gy = a * (p[1] - m[1]) + d * ((p[2] - m[2]) + (p[0] - m[0]));
+}
 
 }  // namespace lbm

@@ -131,10 +131,15 @@ __device__ inline double force_from(double phic, double g, double gu, double A) 
 // stencil radii staged along x and y (>= the domain's taps along each axis).
 // `tabs` is LDS for the two sign-folded coefficient tables (2 TAB doubles),
 // staged here from the domain's device tables.
-template <typename Real, int FORCE, int TX, int TY, int K, int RX, int RY>
+// With G9 the gradient is Eq. 15 (the 3 x 3 neighbourhood of every collision
+// cell): the potential is staged over the block of rows y0-2 .. y0+TY+1 and
+// columns x0-2 .. x0+TX+1 (in the column-bar area) instead of the cross.
+template <typename Real, int FORCE, int TX, int TY, int K, int RX, int RY, bool G9 = false>
 __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, double* sm, double* tabs) {
     using S = FusedShape<Real, TX, TY, K, RX, RY>;
     constexpr int CW = S::CW, CH = S::CH;
+    constexpr int B9W = CW + 2, B9 = (CH + 2) * B9W;  // Eq. 15 block: pitch, elements
+    static_assert(B9 <= S::VH * CW, "the Eq. 15 block must fit the column-bar area");
     double* rowr = sm;                          // [CH][RW]   phi rows  x0-1-RX .. x0+TX+RX (+ segment padding)
     double* colr = rowr + CH * S::RW;           // [VH][CW]   phi cols  y0-1-RY .. y0+TY+RY (+ segment padding)
     Real* fst = reinterpret_cast<Real*>(sm);    // [Q][CH][CW] post-collision populations (after phase 2)
@@ -156,16 +161,25 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     // also wait for the populations).
     StageRegs<CH * S::RW> srow;
     StageRegs<S::VH * CW> scol;
-    stage_issue(srow, tid, [&](int i) {
-        const int r = i / S::RW, c = i - r * S::RW;
-        const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
-        return (double)phin[(long)yw * pitch + xw];
-    });
-    stage_issue(scol, tid, [&](int i) {
-        const int r = i / CW, c = i - r * CW;
-        const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
-        return (double)phin[(long)yw * pitch + xw];
-    });
+    if constexpr (G9) {
+        stage_issue(scol, tid, [&](int i) {
+            const int j = min(i, B9 - 1);  // past the block: a duplicate, not read
+            const int r = j / B9W, c = j - r * B9W;
+            const int yw = wrap(y0 - 2 + r, ny), xw = wrap(x0 - 2 + c, nx);
+            return (double)phin[(long)yw * pitch + xw];
+        });
+    } else {
+        stage_issue(srow, tid, [&](int i) {
+            const int r = i / S::RW, c = i - r * S::RW;
+            const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
+            return (double)phin[(long)yw * pitch + xw];
+        });
+        stage_issue(scol, tid, [&](int i) {
+            const int r = i / CW, c = i - r * CW;
+            const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
+            return (double)phin[(long)yw * pitch + xw];
+        });
+    }
 
     // Keep the compiler from moving cross loads behind population loads.
     __builtin_amdgcn_sched_barrier(0);
@@ -185,7 +199,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 1: the cross and the coefficient tables into LDS.
-    stage_commit(rowr, tid, srow);
+    if constexpr (!G9) stage_commit(rowr, tid, srow);
     stage_commit(colr, tid, scol);
     for (int i = tid; i < TAB; i += NT) {
         tabs[i] = a.tab->tx_tab[i];
@@ -195,9 +209,34 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
 
     // Phase 2: gradients and force.  Axes longer than 2R + 1 use the geometric
     // recursion (one segment of SX outputs per x item, a whole collision
-    // column per y item); shorter axes the explicit K-blocked window.
-    const int nix = a.rec_x ? S::RITEMS_X : S::ITEMS_X;
-    const int niy = a.rec_y ? S::RITEMS_Y : S::ITEMS_Y;
+    // column per y item); shorter axes the explicit K-blocked window.  With
+    // G9, Eq. 15 over each collision cell's neighbourhood.
+    if constexpr (G9) {
+        auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
+        auto opu = [](double v) { return v * fabs(v); };
+        for (int c = tid; c < S::NCELL; c += NT) {
+            const int cy = c / CW, cx = c - cy * CW;
+            const double* b = colr + cy * B9W + cx;  // block row cy (lattice row y-1), column cx (x-1)
+            double m[3], ce[3], pl[3], mu[3], cu[3], pu[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                m[k] = op(b[k]);
+                ce[k] = op(b[B9W + k]);
+                pl[k] = op(b[2 * B9W + k]);
+                mu[k] = opu(b[k]);
+                cu[k] = opu(b[B9W + k]);
+                pu[k] = opu(b[2 * B9W + k]);
+            }
+            double gx, gy, gxu = 0.0, gyu = 0.0;
+            grad_d2q9(m, ce, pl, gx, gy);
+            if (FORCE == FORCE_HYBRID) grad_d2q9(mu, cu, pu, gxu, gyu);
+            const double phic = b[B9W + 1];
+            Fx[c] = force_from<FORCE>(phic, gx, gxu, a.A);
+            Fy[c] = force_from<FORCE>(phic, gy, gyu, a.A);
+        }
+    }
+    const int nix = G9 ? 0 : (a.rec_x ? S::RITEMS_X : S::ITEMS_X);
+    const int niy = G9 ? 0 : (a.rec_y ? S::RITEMS_Y : S::ITEMS_Y);
     // y items start at a wavefront boundary so that no wavefront runs both
     // the x and the y branch (they would execute one after the other).
     const int ybase = (nix + BX - 1) & ~(BX - 1);
@@ -300,14 +339,14 @@ __device__ inline int xcd_tile(int b, int G) {
     return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
 }
 
-template <typename Real, int FORCE, int TX, int TY, int K>
+template <typename Real, int FORCE, int TX, int TY, int K, bool G9 = false>
 __global__ void __launch_bounds__(NT) k_fused(StepArgs<Real> a) {
     constexpr int R = Radius<Real>::value;
     __shared__ double sm[FusedShape<Real, TX, TY, K, R, R>::DOUBLES];
     __shared__ double tabs[2 * TAB];
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     const int ty = t / gridDim.x, tx = t - ty * gridDim.x;
-    fused_tile<Real, FORCE, TX, TY, K, R, R>(a, tx * TX, ty * TY, sm, tabs);
+    fused_tile<Real, FORCE, TX, TY, K, R, R, G9>(a, tx * TX, ty * TY, sm, tabs);
 }
 
 // Batched step: one launch advances every domain of a batch by one step.
@@ -320,7 +359,7 @@ struct BatchTile {
     int d, x0, y0, pad;
 };
 
-template <typename Real, int FORCE, int TY, int RY>
+template <typename Real, int FORCE, int TY, int RY, bool G9 = false>
 __global__ void __launch_bounds__(NT) k_batch(const StepArgs<Real>* __restrict__ descs,
                                               const BatchTile* __restrict__ tiles, int ntiles) {
     constexpr int RX = Radius<Real>::value;
@@ -328,7 +367,7 @@ __global__ void __launch_bounds__(NT) k_batch(const StepArgs<Real>* __restrict__
     __shared__ double tabs[2 * TAB];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const BatchTile w = tiles[t];
-        fused_tile<Real, FORCE, BX, TY, 4, RX, RY>(descs[w.d], w.x0, w.y0, sm, tabs);
+        fused_tile<Real, FORCE, BX, TY, 4, RX, RY, G9>(descs[w.d], w.x0, w.y0, sm, tabs);
         __syncthreads();
     }
 }
@@ -359,7 +398,10 @@ __global__ void __launch_bounds__(NT) k_batch_finite(const StepArgs<Real>* __res
 template <typename Real, int FORCE, int TX, int TY, int K>
 inline void launch_fused_t(const StepArgs<Real>& a, hipStream_t s) {
     dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_fused<Real, FORCE, TX, TY, K>), grid, dim3(NT), 0, s, a);
+    if (a.grad9)
+        hipLaunchKernelGGL((k_fused<Real, FORCE, TX, TY, K, true>), grid, dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fused<Real, FORCE, TX, TY, K>), grid, dim3(NT), 0, s, a);
 }
 
 // Tile choice: FP64 storage uses 64 x 8 tiles (two workgroups per CU fit in

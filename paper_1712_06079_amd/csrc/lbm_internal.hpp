@@ -92,6 +92,7 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     a.rr3 = a.rr * a.rr * a.rr;
     a.rr4 = a.rr3 * a.rr;
     a.rK = C / (1.0 - a.rr);
+    a.grad9 = d->p.grad == LBM_GRAD_CDM9 ? 1 : 0;
     return a;
 }
 

@@ -157,10 +157,54 @@ __device__ inline void stage_cross(Cross<Real, TY>& s, const P* __restrict__ phi
 //  SC (Eq. 22): F = -2 s Phi D Phi = -2 phi(x) D|phi|
 //  ZC (Eq. 7):  F = -D U
 //  hybrid (Eq. 9): A F^ZC + (1 - 2A) F^SC with U = phi |phi|.
+// The 3 x 3 neighbourhoods of a 64 x TY tile for Eq. 15: rows y0-1 .. y0+TY,
+// columns x0-1 .. x0+64, periodic.
+template <int TY>
+struct Block9 {
+    static constexpr int W = BX + 2;
+    double v[TY + 2][W];
+};
+
+template <int TY, typename P>
+__device__ inline void stage_block9(Block9<TY>& b, const P* __restrict__ phi, int x0, int y0, int nx, int ny, int pitch) {
+    stage_lds<(TY + 2) * Block9<TY>::W, 8>(&b.v[0][0], [&](int i) {
+        const int r = i / Block9<TY>::W, c = i - r * Block9<TY>::W;
+        return (double)phi[(long)wrap(y0 - 1 + r, ny) * pitch + wrap(x0 - 1 + c, nx)];
+    });
+}
+
 template <typename Real, int FORCE, int TY>
-__device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& a, int r, int lx, double& Fx, double& Fy) {
+__device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& a, int r, int lx, double& Fx, double& Fy,
+                                const Block9<TY>* b9 = nullptr) {
     constexpr int J = Cross<Real, TY>::J;
     const double pc = s.row[r][J + lx];
+    if (a.grad9) {  // Eq. 15 over the neighbourhood (b9 staged when grad9)
+        auto op = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
+        double m[3], c[3], p[3], mu[3], cu[3], pu[3];
+        for (int k = 0; k < 3; ++k) {
+            m[k] = op(b9->v[r][lx + k]);
+            c[k] = op(b9->v[r + 1][lx + k]);
+            p[k] = op(b9->v[r + 2][lx + k]);
+            mu[k] = b9->v[r][lx + k] * fabs(b9->v[r][lx + k]);
+            cu[k] = b9->v[r + 1][lx + k] * fabs(b9->v[r + 1][lx + k]);
+            pu[k] = b9->v[r + 2][lx + k] * fabs(b9->v[r + 2][lx + k]);
+        }
+        double gx, gy, gxu = 0.0, gyu = 0.0;
+        grad_d2q9(m, c, p, gx, gy);
+        if (FORCE == FORCE_HYBRID) grad_d2q9(mu, cu, pu, gxu, gyu);
+        if (FORCE == FORCE_ZC) {
+            Fx = -gx;
+            Fy = -gy;
+        } else {
+            Fx = -2.0 * pc * gx;
+            Fy = -2.0 * pc * gy;
+            if (FORCE == FORCE_HYBRID) {
+                Fx = a.A * (-gxu) + (1.0 - 2.0 * a.A) * Fx;
+                Fy = a.A * (-gyu) + (1.0 - 2.0 * a.A) * Fy;
+            }
+        }
+        return;
+    }
     if (FORCE == FORCE_ZC) {
         double gx = 0, gy = 0;
         for (int j = 1; j <= a.tx; ++j) gx += a.tab->dx[j - 1] * (s.row[r][J + lx + j] - s.row[r][J + lx - j]);
@@ -194,17 +238,19 @@ __device__ inline void force_at(const Cross<Real, TY>& s, const StepArgs<Real>& 
 template <typename Real, int FORCE, int TY>
 __global__ void __launch_bounds__(NT) k_collide(StepArgs<Real> a) {
     __shared__ Cross<Real, TY> s;
+    __shared__ Block9<TY> b9;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
-    stage_cross<Real, TY>(s, static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in), x0, y0, a.nx, a.ny,
-                          pitch);
+    const auto* phin = static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in);
+    stage_cross<Real, TY>(s, phin, x0, y0, a.nx, a.ny, pitch);
+    if (a.grad9) stage_block9<TY>(b9, phin, x0, y0, a.nx, a.ny, pitch);
     __syncthreads();
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
         const int y = y0 + r;
         if (y >= a.ny) break;
         double Fx, Fy;
-        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
+        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy, &b9);
         if (x >= a.nx) continue;
         double f[Q];
 #pragma unroll
@@ -243,10 +289,12 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
                                                 double* __restrict__ partial) {
     __shared__ Cross<Real, TY> s;
     __shared__ double red[4][NT / BX];
+    __shared__ Block9<TY> b9;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
-    stage_cross<Real, TY>(s, static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in), x0, y0, a.nx, a.ny,
-                          pitch);
+    const auto* phin = static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in);
+    stage_cross<Real, TY>(s, phin, x0, y0, a.nx, a.ny, pitch);
+    if (a.grad9) stage_block9<TY>(b9, phin, x0, y0, a.nx, a.ny, pitch);
     __syncthreads();
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
     double m = 0, px = 0, py = 0, vmax = 0;
@@ -254,7 +302,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
         const int y = y0 + r;
         if (y >= a.ny) break;
         double Fx, Fy;
-        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy);
+        force_at<Real, FORCE, TY>(s, a, r, lx, Fx, Fy, &b9);
         if (x >= a.nx) continue;
         double f[Q];
 #pragma unroll

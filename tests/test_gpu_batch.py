@@ -112,6 +112,53 @@ def test_autotune_restores_state_and_picks_a_candidate():
         assert np.array_equal(a.domain(i).populations().cpu().numpy(), ref.domain(i).populations().cpu().numpy()), i
 
 
+def test_schedule_change_after_steps_on_a_side_stream():
+    """Steps queued on a side stream, then a new schedule given that stream:
+    the queued steps finish with the old worklist before it is replaced."""
+    ps, rhos = sweep_params(8, 15, "f64", SHAPES)
+    a = L.Batch(ps, [dev(r) for r in rhos])
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        a.step(40, stream=side)
+        a.set_schedule(4, 2, 64, stream=side)
+        a.step(17, stream=side)
+    side.synchronize()
+    ref = L.Batch(ps, [dev(r) for r in rhos])
+    ref.step(57)
+    for i in range(len(ps)):
+        assert np.array_equal(a.domain(i).populations().cpu().numpy(), ref.domain(i).populations().cpu().numpy()), i
+
+
+@pytest.mark.parametrize("force", ["sc", "hybrid"])
+def test_cdm9_batch(force):
+    """A batch of Eq. 15 domains (the hybrid with a different weight A per
+    domain): bitwise the single-domain kernel, and the oracle within 1e-12."""
+    ps, rhos = sweep_params(8, 17, "f64", SHAPES)
+    for i, p in enumerate(ps):
+        p.grad, p.force = "cdm9", force
+        p.A = 0.02 * (i - 4) if force == "hybrid" else 0.0
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    b.step(25)
+    for i, (p, r) in enumerate(zip(ps, rhos)):
+        d = L.Domain(p, dev(r))
+        d.step(25)
+        assert np.array_equal(b.domain(i).populations().cpu().numpy(), d.populations().cpu().numpy()), i
+    for i in (1, 6):
+        po = to_oracle(ps[i])
+        ref = O.moments(po, O.run(po, O.init(po, rhos[i]), 25))["rho"]
+        got = b.domain(i).moments()["rho"].cpu().numpy()
+        assert np.max(np.abs(got - ref) / ref) < 1e-12, i
+
+
+def test_batch_rejects_mixed_eq15():
+    ps, rhos = sweep_params(4, 19, "f64", ([128, 64, 64, 128], [8, 8, 16, 8]))
+    ps[2].grad = "cdm9"
+    with pytest.raises(L.LBMError) as e:
+        L.Batch(ps, [dev(r) for r in rhos])
+    assert e.value.status == 1
+
+
 def test_per_domain_nonfinite_flags():
     ps, rhos = sweep_params(8, 13, "f64", SHAPES)
     b = L.Batch(ps, [dev(r) for r in rhos])
@@ -158,3 +205,53 @@ def test_full_coexistence_sweep():
         ref = O.moments(po, O.run(po, O.init(po, rhos[i]), n))["rho"]
         got = b.domain(i).moments()["rho"].cpu().numpy()
         assert np.max(np.abs(got - ref) / ref) < 1e-12, i
+
+
+COEX_EOS = {"vdw": dict(a=9 / 49, b=2 / 21, k=0.01), "rk": dict(a=9 / 49, b=2 / 21, k=0.02),
+            "pr": dict(a=9 / 49, b=2 / 21, k=0.04, omega=0.344), "cs": dict(a=1.0, b=4.0, k=0.04)}
+
+
+def _coexistence_run(force, grad, trs, steps=20000, nx=256, ny=8):
+    ps, rhos, maxw = [], [], []
+    for eos, c in COEX_EOS.items():
+        for tr in trs:
+            p = L.Params(nx=nx, ny=ny, eos=eos, force=force, grad=grad, R=1.0, tau=1.6, **c)
+            tc, _ = L.critical(p)
+            p.T = tr * tc
+            rv, rl, _ = L.maxwell(p, p.T)
+            ps.append(p)
+            maxw.append((rv, rl))
+            rhos.append(I.slab(nx, ny, rv, rl, 5.0, axis="x", noise=1e-4 * rv, seed=7))
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    b.step(steps)
+    assert not any(b.check_finite()), (force, grad)
+    out = []
+    for i, p in enumerate(ps):
+        rho = b.domain(i).moments(want=("rho",))["rho"].mean(dim=0).cpu().numpy()
+        w = nx // 8
+        rl = rho[nx // 2 - w // 2:nx // 2 - w // 2 + w].mean()
+        rv = np.concatenate([rho[:w // 2 + 1], rho[nx - w // 2:]]).mean()
+        out.append((rl / maxw[i][1] - 1, rv / maxw[i][0] - 1))
+    return np.array(out)
+
+
+def test_coexistence_against_maxwell():
+    """Sec. 5.2 (Fig. 5): flat interfaces of the van der Waals, Redlich-Kwong,
+    PR-water and Carnahan-Starling fluids (the paper's constants and k,
+    tau = 1.6) at T_r = 0.7, 0.8, 0.9 after 20 000 steps.  With the high-order
+    difference, Shan-Chen and Zhang-Chen alike, the liquid density is within
+    0.1 % and the vapour density within 10 % of the Maxwell rule (measured:
+    within 7e-5 and 9.3 %, the largest for PR at 0.7), and the two forces agree
+    with each other; the weighted central difference (Eq. 15) misses the vapour
+    density by at least three times as much at every point.  (Below T_r = 0.7
+    the vapour error of the high-order difference grows for RK and PR, in the
+    oracle too: the bar is stated where the method meets it.)"""
+    trs = (0.7, 0.8, 0.9)
+    sc = _coexistence_run("sc", "hdm", trs)
+    zc = _coexistence_run("zc", "hdm", trs)
+    cdm = _coexistence_run("sc", "cdm9", trs)
+    for e in (sc, zc):
+        assert np.max(np.abs(e[:, 0])) < 1e-3, e
+        assert np.max(np.abs(e[:, 1])) < 0.10, e
+    assert np.max(np.abs(sc[:, 1] - zc[:, 1])) < 0.02, (sc, zc)
+    assert np.all(np.abs(cdm[:, 1]) > 3 * np.maximum(np.abs(sc[:, 1]), np.abs(zc[:, 1]))), (sc, zc, cdm)

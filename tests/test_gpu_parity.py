@@ -208,7 +208,55 @@ def test_cdm_gradient():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_moments_match_oracle(prec):
+@pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
+def test_cdm9_gradient(force, prec):
+    """The weighted D2Q9 difference of Eq. 15 (with the 1/c_s^2 factor) on the
+    tile kernel: every force, ragged 70 x 37 droplet with velocity noise, 60
+    steps."""
+    po, rho0, ux0, uy0 = variant_case("vdw", force, 70, 37, seed=13)
+    po.grad = "cdm9"
+    ref = oracle_run(po, rho0, 60, ux0, uy0)
+    got = gpu_run(po, rho0, 60, prec, ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("variant,tile", [(2, 4), (2, 8), (2, 16), (1, 8), (1, 16)])
+def test_cdm9_kernel_variants(variant, tile):
+    """Eq. 15 on every tile height and on the two-pass reference kernel.  (The
+    Peng-Robinson droplet the Eq. 20 variants use blows up within 20 steps with
+    either central difference, in the oracle too; the van der Waals one stays
+    bounded.)"""
+    po, rho0, ux0, uy0 = variant_case("vdw", "zc", 150, 70, seed=5)
+    po.grad = "cdm9"
+    ref = oracle_run(po, rho0, 30, ux0, uy0)
+    got = gpu_run(po, rho0, 30, "f64", ux0, uy0, variant=variant, tile=tile)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+    assert np.max(np.abs(got["f"] - ref["f"])) < 1e-12 * np.max(np.abs(ref["f"]))
+
+
+def test_cdm9_unsupported_paths():
+    """Eq. 15 has no geometric form: the marching kernel rejects it, and so does
+    the reverse step (its kernels implement the per-axis stencils)."""
+    po, rho0, _, _ = variant_case("cs", "sc", 64, 128, seed=2)
+    po.grad = "cdm9"
+    d = L.Domain(lib_params(po), dev(rho0))
+    d.set_kernel(3, 8)
+    with pytest.raises(L.LBMError) as e:
+        d.step(1)
+    assert e.value.status == 5
+    d.set_kernel(0, 0)
+    st = d.new_states(1)
+    d.save_state(st[0])
+    lam = torch.zeros((9, 128, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LBMError) as e:
+        d.adjoint_step(st[0], lam, torch.empty_like(lam), torch.zeros(2, dtype=torch.float64, device="cuda"),
+                       d.adjoint_workspace())
+    assert e.value.status == 5
+
+
+@pytest.mark.parametrize("grad", ["hdm", "cdm9"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_moments_match_oracle(prec, grad):
     """Half-step velocity (Eq. 11), bulk pressure and the fixed-order totals,
     element by element.  v = (j + F/2) / rho is a difference of sums of size
     rho (j sums the positive populations with signs) plus the force, so its
@@ -216,6 +264,7 @@ def test_moments_match_oracle(prec):
     bulk pressure p = rho/3 + U(rho) by the tolerance times
     rho/3 + |U| + rho |dU/drho| (the density error carried through U)."""
     po, rho0, ux0, uy0 = variant_case("vdw", "sc", 96, 80, seed=4)
+    po.grad = grad
     ref = oracle_run(po, rho0, 100, ux0, uy0)
     got = gpu_run(po, rho0, 100, prec, ux0, uy0)
     tol = TOL[prec]
