@@ -377,6 +377,51 @@ int maxwell(const orc_params& p, double T, double* rho_v, double* rho_l, double*
     return 0;
 }
 
+// ---------------------------------------------------------------- Sec. 5.1, Eqs. 25-26
+// Flat interface along y in the fluid of Eq. 25 (square-gradient pressure
+// tensor with constant kappa) with the k-scaled EOS p_m = k p_EOS (Sec. 5).
+// Mechanical equilibrium (Eq. 26) in a flat interface leaves one component:
+//   P_yy = p_m(rho) - kappa rho rho'' - (kappa/2) rho'^2 + kappa rho'^2
+// is uniform and equal to the bulk (coexistence) pressure k p0.  Its first
+// integral is (kappa/2) rho'^2 = W(rho) with
+//   W(rho) = rho * integral_{rho_b}^{rho} (p_m(s) - k p0) / s^2 ds,
+// where rho_b may be either bulk density (the integral between them vanishes:
+// the equal-area rule), so rho' = sqrt(2 W / kappa) where rho rises with y.
+// (Differentiating: kappa rho'' = W'(rho) = W/rho + p_m - k p0, which puts
+// P_yy back to k p0.)
+struct Interface {
+    Isotherm iso;
+    double k, p0, rv, rl;
+};
+
+bool make_interface(const orc_params& p, Interface* f) {
+    CritResult c = critical_point(p);
+    if (!c.ok || !(p.T > 0.0) || p.T >= c.Tc) return false;
+    f->iso = Isotherm{p, p.T, alpha_of<double>(p, p.T, c.Tc)};
+    f->k = p.k;
+    return maxwell(p, p.T, &f->rv, &f->rl, &f->p0) == 0;
+}
+
+// W(rho) by composite 8-point Gauss-Legendre from the nearer bulk density.
+double excess_W(const Interface& f, double rho) {
+    const double ref = (rho > 0.5 * (f.rv + f.rl)) ? f.rl : f.rv;
+    const int NP = 64;
+    const double hs = (rho - ref) / NP;
+    double sum = 0.0;
+    for (int k = 0; k < NP; ++k) {
+        const double c = ref + (k + 0.5) * hs;
+        for (int j = 0; j < 8; ++j) {
+            const double s = c + 0.5 * hs * GL8_X[j];
+            sum += 0.5 * hs * GL8_W[j] * f.k * (f.iso.P(s) - f.p0) / (s * s);
+        }
+    }
+    const double W = rho * sum;
+    return W > 0.0 ? W : 0.0;  // W >= 0; only rounding takes it below zero next to a bulk density
+}
+
+// d rho / dy on the rising interface.
+double slope(const Interface& f, double kappa, double rho) { return std::sqrt(2.0 * excess_W(f, rho) / kappa); }
+
 // ---------------------------------------------------------------- Sec. 3 stencils
 // High-order difference, Eq. 20 with h = 1 on a periodic line of n points:
 //   (1/3) y_{i-1} + y_i + (1/3) y_{i+1} = (1/36)(u_{i+2} - u_{i-2}) + (7/9)(u_{i+1} - u_{i-1}).
@@ -752,6 +797,62 @@ void orc_collide_cell(const double* f9, double Fx, double Fy, double tau, double
     for (int i = 1; i < 9; ++i) rho += f9[i];
     for (int i = 0; i < 9; ++i) { jx += EX[i] * f9[i]; jy += EY[i] * f9[i]; }
     collide_cell<double>(f9, rho, jx, jy, Fx, Fy, tau, out9);
+}
+
+// "Exact" flat-interface profile of Sec. 5.1 (Eqs. 25-26): rho and rho' at
+// y_i = (i - (n - 1)/2) h, i < n, for the interface rising with y through
+// rho(0) = (rho_v + rho_l)/2.  Classic fourth-order Runge-Kutta on
+// rho' = sqrt(2 W(rho) / kappa) from y = 0 outwards, steps of at most h/16.
+int orc_flat_profile(const orc_params* p, double kappa, double h, int n, double* rho, double* drho) {
+    Interface f;
+    if (!(kappa > 0.0) || !(h > 0.0) || n < 1 || !make_interface(*p, &f)) return 1;
+    auto F = [&](double r) { return slope(f, kappa, r); };
+    const double c = 0.5 * (n - 1);
+    for (int dir = -1; dir <= 1; dir += 2) {
+        double y = 0.0, r = 0.5 * (f.rv + f.rl);
+        // grid points on this side, nearest first (y = 0 itself on the upper side)
+        for (int i = (dir > 0) ? (int)std::ceil(c) : (int)std::ceil(c) - 1; i >= 0 && i < n; i += dir) {
+            const double yt = (i - c) * h;
+            const int m = (int)std::ceil(std::fabs(yt - y) / (h / 16.0));
+            const double dy = (m > 0) ? (yt - y) / m : 0.0;
+            for (int s = 0; s < m; ++s) {
+                const double k1 = F(r), k2 = F(r + 0.5 * dy * k1), k3 = F(r + 0.5 * dy * k2), k4 = F(r + dy * k3);
+                r += dy * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+            }
+            y = yt;
+            rho[i] = r;
+            drho[i] = F(r);
+        }
+    }
+    return 0;
+}
+
+// Surface tension by the integration method (Sec. 5.3) with the tensor of
+// Eq. 25: sigma = integral (P_N - P_T) dy = kappa integral rho'^2 dy.  For a
+// periodic column of n sites (h = 1) holding two interfaces (a slab) the
+// derivative is Eq. 20 and each interface gets half of kappa sum (D rho)^2.
+double orc_sigma_slab(double kappa, int n, const double* rho) {
+    std::vector<double> d(n);
+    hdm_line<double>(n, rho, 1, d.data(), 1);
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += d[i] * d[i];
+    return 0.5 * kappa * sum;
+}
+
+// The same integral in closed form for the exact profile: with
+// (kappa/2) rho'^2 = W, kappa integral rho'^2 dy = integral_{rho_v}^{rho_l} sqrt(2 kappa W) d rho.
+int orc_sigma_exact(const orc_params* p, double kappa, double* sigma) {
+    Interface f;
+    if (!(kappa > 0.0) || !make_interface(*p, &f)) return 1;
+    const int NP = 256;
+    const double hs = (f.rl - f.rv) / NP;
+    double sum = 0.0;
+    for (int k = 0; k < NP; ++k) {
+        const double c = f.rv + (k + 0.5) * hs;
+        for (int j = 0; j < 8; ++j) sum += 0.5 * hs * GL8_W[j] * std::sqrt(2.0 * kappa * excess_W(f, c + 0.5 * hs * GL8_X[j]));
+    }
+    *sigma = sum;
+    return 0;
 }
 
 // Initial state f = f^eq(rho0, u0) (Eq. 2); ux0 / uy0 may be NULL (u0 = 0).

@@ -61,6 +61,12 @@ def load(path: str):
     L.orc_hdm_line.argtypes = [C.c_int, _D, _D]
     L.orc_cdm_line.argtypes = [C.c_int, _D, _D]
     L.orc_gradient.argtypes = [P, _D, _D, _D]
+    L.orc_flat_profile.argtypes = [P, C.c_double, C.c_double, C.c_int, _D, _D]
+    L.orc_flat_profile.restype = C.c_int
+    L.orc_sigma_slab.argtypes = [C.c_double, C.c_int, _D]
+    L.orc_sigma_slab.restype = C.c_double
+    L.orc_sigma_exact.argtypes = [P, C.c_double, _D]
+    L.orc_sigma_exact.restype = C.c_int
     L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, _D]
     L.orc_collide_cell.argtypes = [_D, C.c_double, C.c_double, C.c_double, _D]
     L.orc_init.argtypes = [P, _D, _D, _D, _D]
@@ -149,6 +155,29 @@ def gradient(p: Params, u):
     gx, gy = np.empty_like(u), np.empty_like(u)
     lib().orc_gradient(C.byref(p.c()), _ptr(u), _ptr(gx), _ptr(gy))
     return gx, gy
+
+
+def flat_profile(p: Params, kappa: float, h: float, n: int):
+    """Exact flat-interface profile of Eqs. 25-26 with the k-scaled EOS:
+    (y, rho, drho/dy) at y_i = (i - (n-1)/2) h, rising through the mean density at y = 0."""
+    rho, drho = np.empty(n), np.empty(n)
+    if lib().orc_flat_profile(C.byref(p.c()), kappa, h, n, _ptr(rho), _ptr(drho)):
+        raise ValueError("no flat interface for these parameters")
+    return (np.arange(n) - 0.5 * (n - 1)) * h, rho, drho
+
+
+def sigma_slab(kappa: float, rho_column):
+    """Integration-method surface tension of one interface of a periodic slab column (h = 1)."""
+    r = np.ascontiguousarray(rho_column, dtype=np.float64)
+    return float(lib().orc_sigma_slab(kappa, len(r), _ptr(r)))
+
+
+def sigma_exact(p: Params, kappa: float):
+    """integral sqrt(2 kappa W) d rho: the integration method on the exact profile."""
+    s = C.c_double()
+    if lib().orc_sigma_exact(C.byref(p.c()), kappa, C.byref(s)):
+        raise ValueError("no flat interface for these parameters")
+    return s.value
 
 
 def feq(rho, ux, uy):

@@ -627,6 +627,60 @@ def pin_adjoint_checkpoint_invariance():
     assert a["dg"] == b["dg"] == c["dg"] and a["dT"] == b["dT"] == c["dT"]
 
 
+# ------------------------------------------------------------------ Sec. 5.1, Eqs. 25-26
+def pin_flat_profile_satisfies_eq26():
+    """The exact flat-interface profile (VDW, T_r = 0.9, k = 0.01, two kappas)
+    against Eq. 26 itself: with rho' and rho'' taken by sixth-order central
+    differences of the sampled profile (h = 0.05), the normal component of the
+    Eq. 25 tensor, P_yy = k p(rho) - kappa rho rho'' + (kappa/2) rho'^2, is the
+    coexistence pressure k p0 everywhere across the interface; the tails
+    approach the Maxwell densities and the reported slope equals the
+    differenced one."""
+    p = c1_params()
+    rv, rl, p0 = O.maxwell(p, p.T)
+    for kappa in (0.004, 0.02):
+        h = 0.05
+        y, r, d = O.flat_profile(p, kappa, h, 1601)
+        c6 = np.array([-1, 9, -45, 0, 45, -9, 1]) / 60.0
+        s6 = np.array([2, -27, 270, -490, 270, -27, 2]) / 180.0
+        i = np.arange(3, len(r) - 3)
+        d1 = sum(c6[k] * r[i + k - 3] for k in range(7)) / h
+        d2 = sum(s6[k] * r[i + k - 3] for k in range(7)) / h ** 2
+        pm = np.array([p.k * O.eos(p, float(x), p.T)[0] for x in r[i]])
+        Pyy = pm - kappa * r[i] * d2 + 0.5 * kappa * d1 ** 2
+        assert np.max(np.abs(Pyy - p.k * p0)) < 1e-7 * p.k * p0, (kappa, np.max(np.abs(Pyy - p.k * p0)) / (p.k * p0))
+        assert np.max(np.abs(d1 - d[i])) < 1e-6 * d.max(), kappa
+        assert abs(r[0] / rv - 1) < 1e-3 and abs(r[-1] / rl - 1) < 1e-3, (kappa, r[0], r[-1])
+        assert np.all(np.diff(r) > 0)
+
+
+def pin_integration_method_sigma():
+    """Sec. 5.3's integration method on the exact profile: sigma = kappa
+    integral rho'^2 dy (trapezoids on the sampled profile) equals the closed
+    form integral sqrt(2 kappa W) d rho; and on a periodic slab of two such
+    interfaces sampled at h = 1 with the derivative of Eq. 20 it gives the
+    same value per interface."""
+    p = c1_params()
+    rv, rl, _ = O.maxwell(p, p.T)
+    kappa = 0.02
+    y, r, d = O.flat_profile(p, kappa, 0.02, 4001)
+    s_trapz = kappa * np.trapezoid(d ** 2, y)
+    s_exact = O.sigma_exact(p, kappa)
+    assert abs(s_trapz / s_exact - 1) < 1e-6, (s_trapz, s_exact)
+    _, r1, _ = O.flat_profile(p, kappa, 1.0, 81)
+    slab = np.concatenate([r1, r1[::-1]])  # rising then falling: a periodic slab of 162 sites
+    assert abs(O.sigma_slab(kappa, slab) / s_exact - 1) < 1e-3, (O.sigma_slab(kappa, slab), s_exact)
+
+
+def pin_sigma_critical_exponent():
+    """Close to the critical point the square-gradient van der Waals fluid has
+    the mean-field surface tension law sigma ~ (1 - T_r)^(3/2) (the theory value
+    the paper's fitted exponent 1.49 is compared with, Sec. 5.3)."""
+    s1 = O.sigma_exact(c1_params(T=(1 - 2e-3) * VDW_TC), 0.01)
+    s2 = O.sigma_exact(c1_params(T=(1 - 1e-3) * VDW_TC), 0.01)
+    assert abs(np.log(s1 / s2) / np.log(2.0) - 1.5) < 0.01, np.log(s1 / s2) / np.log(2.0)
+
+
 # ------------------------------------------------------------------ Sec. 5.3, Table 1
 def laplace_sigma(tr, R=32, n=128, steps=8000):
     """Surface tension from Laplace's law on one droplet: sigma = (p_in - p_out) R_e,
@@ -660,5 +714,6 @@ FAST = [
     pin_x_invariance, pin_shift_equivariance, pin_mirror_symmetry, pin_shear_wave_viscosity,
     pin_flat_interface_equilibrium, pin_tangent_matches_differences, pin_adjoint_dot_product,
     pin_adjoint_finite_differences, pin_adjoint_checkpoint_invariance, pin_hybrid_limits,
+    pin_flat_profile_satisfies_eq26, pin_integration_method_sigma, pin_sigma_critical_exponent,
 ]
 SLOW = [pin_maxwell_equal_area, pin_hdm_beats_cdm_coexistence, pin_table1_laplace]

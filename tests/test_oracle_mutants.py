@@ -75,6 +75,15 @@ MUTANTS = {
     "d2q9_dropped_diagonals": ("for (int i = 1; i < 9; ++i) {\n                const int e", "for (int i = 1; i < 5; ++i) {\n                const int e"),
     "d2q9_neighbour_index": ("const int xn = (x + EX[i] + nx) % nx, yn = (y + EY[i] + ny) % ny;",
                              "const int xn = (x + EX[i] + nx) % nx, yn = (y - EY[i] + ny) % ny;"),
+    "excess_W_measure": ("sum += 0.5 * hs * GL8_W[j] * f.k * (f.iso.P(s) - f.p0) / (s * s);",
+                         "sum += 0.5 * hs * GL8_W[j] * f.k * (f.iso.P(s) - f.p0) / s;"),
+    "excess_W_without_p0": ("sum += 0.5 * hs * GL8_W[j] * f.k * (f.iso.P(s) - f.p0) / (s * s);",
+                            "sum += 0.5 * hs * GL8_W[j] * f.k * f.iso.P(s) / (s * s);"),
+    "interface_slope_factor": ("return std::sqrt(2.0 * excess_W(f, rho) / kappa);", "return std::sqrt(excess_W(f, rho) / kappa);"),
+    "profile_low_order_steps": ("r += dy * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;", "r += dy * k1;"),
+    "sigma_slab_both_interfaces": ("return 0.5 * kappa * sum;", "return kappa * sum;"),
+    "sigma_exact_without_two": ("std::sqrt(2.0 * kappa * excess_W(f, c + 0.5 * hs * GL8_X[j]))",
+                                "std::sqrt(kappa * excess_W(f, c + 0.5 * hs * GL8_X[j]))"),
     # Eq. 9 weights, changed consistently in the forward force and its adjoint
     # (a mistake made in both passes survives the dot-product identity)
     "hybrid_sc_weight_both_passes": ("(1.0 - 2.0 * m.p.A)", "(1.0 - m.p.A)"),
