@@ -330,12 +330,114 @@ def fig5_coexistence(steps: int = 60000, nx: int = 256, ny: int = 8):
     return out
 
 
+# Table 1 of the paper (van der Waals fluid): integration-method and
+# Laplace-law surface tensions at T_r = 0.4 .. 0.8.
+TABLE1 = {0.4: (0.10885, 0.11032), 0.5: (0.08457, 0.08544), 0.6: (0.06151, 0.06176), 0.7: (0.04044, 0.04032),
+          0.8: (0.02221, 0.02186)}
+
+
+def surface_tension_report(slab_steps: int = 40000, drop_steps: int = 20000):
+    """Sec. 5.1 and Table 1 for the van der Waals fluid (a = 9/49, b = 2/21,
+    k = 0.01, tau = 1, SC + HDM): flat slabs (8 x 256, y-normal, W = 5) and
+    droplets (R = 32 on 128^2, W = 4) at T_r = 0.4 .. 0.9, one batched run each.
+    kappa of Eq. 25 is read from the simulated interface at T_r = 0.9 (the
+    Fig. 4 case): the value for which the exact profile has the slab's steepest
+    slope, kappa = 2 max W / max rho'^2.  Reports, per T_r, sigma_S by the
+    integration method on the simulated slab (lbm_sigma_slab), the same on the
+    exact profile (integral sqrt(2 kappa W) d rho), sigma_L by Laplace's law
+    (p_in - p_out) R_e with the equimolar radius, the paper's Table 1 values,
+    the kappa that would give the paper's sigma_S, and the exponent fits of
+    sigma ~ (1 - T_r)^e; and the Fig. 4 comparison: derivatives of the exact
+    T_r = 0.9 profile sampled at h = 0.5 (and 1) by Eq. 14 and Eq. 20 against
+    the exact rho', max (E_r, Eq. 17) and RMS (Err, Eq. 18) errors."""
+    import torch
+
+    import paper_1712_06079_amd as L
+    trs = (0.4, 0.5, 0.6, 0.7, 0.8, 0.9)
+    tc = 8 * (9 / 49) / (27 * (2 / 21))
+
+    def prm(nx, ny, tr):
+        return L.Params(nx=nx, ny=ny, eos="vdw", force="sc", a=9 / 49, b=2 / 21, R=1.0, k=0.01, tau=1.0, T=tr * tc)
+
+    slabs, drops, cols = [], [], {}
+    ps_s = [prm(8, 256, tr) for tr in trs]
+    ps_d = [prm(128, 128, tr) for tr in trs]
+    mx = {tr: L.maxwell(ps_s[i], ps_s[i].T) for i, tr in enumerate(trs)}
+    rs = [torch.from_numpy(I.slab(8, 256, mx[tr][0], mx[tr][1], 5.0, axis="y")).cuda() for tr in trs]
+    rd = [torch.from_numpy(I.droplet(128, 128, mx[tr][0], mx[tr][1], 32.0, 4.0)).cuda() for tr in trs]
+    bs, bd = L.Batch(ps_s, rs), L.Batch(ps_d, rd)
+    bs.step(slab_steps)
+    bd.step(drop_steps)
+    fs, fd = bs.check_finite(), bd.check_finite()
+    for i, tr in enumerate(trs):
+        cols[tr] = None if fs[i] else bs.domain(i).moments(want=("rho",))["rho"].mean(dim=1).cpu().numpy()
+    # kappa from the T_r = 0.9 slab
+    p9 = ps_s[-1]
+    rv9, rl9, _ = mx[0.9]
+    grid = np.linspace(rv9, rl9, 4001)[1:-1]
+    wmax = float(L.interface_excess(p9, grid).max())
+    _, d9 = L.sigma_slab(1.0, cols[0.9])
+    kappa = 2.0 * wmax / float(np.max(np.abs(d9))) ** 2
+    rows, sig_s, sig_l = [], {}, {}
+    for i, tr in enumerate(trs):
+        rv, rl, _ = mx[tr]
+        row = {"T_r": tr, "rho_v": rv, "rho_l": rl, "finite_slab": not fs[i], "finite_droplet": not fd[i]}
+        if cols[tr] is not None:
+            sig_s[tr] = L.sigma_slab(kappa, cols[tr])[0]
+            g = np.linspace(rv, rl, 20001)
+            w = L.interface_excess(prm(8, 8, tr), g[1:-1])
+            row["sigma_S"] = sig_s[tr]
+            row["sigma_S_exact_profile"] = float(np.trapezoid(np.sqrt(2 * kappa * np.concatenate([[0], w, [0]])), g))
+        if not fd[i]:
+            m = bd.domain(i).moments(want=("rho", "p"))
+            rho, pr = m["rho"].cpu().numpy(), m["p"].cpu().numpy()
+            ri, ro = rho[64, 64], rho[0, 0]
+            re = float(np.sqrt(((rho - ro) / (ri - ro)).sum() / np.pi))
+            sig_l[tr] = float((pr[64, 64] - pr[0, 0]) * re)
+            row.update({"sigma_L": sig_l[tr], "R_e": round(re, 3), "dp": float(pr[64, 64] - pr[0, 0])})
+        if tr in TABLE1:
+            row["paper_sigma_S"], row["paper_sigma_L"] = TABLE1[tr]
+            if tr in sig_s:
+                row["kappa_for_paper_sigma_S"] = kappa * (TABLE1[tr][0] / sig_s[tr]) ** 2
+        rows.append(row)
+
+    def expo(sig):
+        t = [tr for tr in (0.4, 0.5, 0.6, 0.7, 0.8) if tr in sig]
+        if len(t) < 3:
+            return None
+        return round(float(np.polyfit(np.log([1 - x for x in t]), np.log([sig[x] for x in t]), 1)[0]), 4)
+
+    # Fig. 4: derivatives of the exact T_r = 0.9 profile sampled at h
+    fig4 = {}
+    for h in (0.5, 1.0):
+        n = int(round(60 / h)) | 1
+        _, r, d = L.flat_profile(p9, kappa, h, n)
+        col = np.concatenate([r, r[::-1]])  # rising then falling: periodic
+        _, dh = L.sigma_slab(kappa, col)
+        dh = dh[:n] / h
+        dc = (np.roll(col, -1) - np.roll(col, 1))[:n] / (2 * h)
+        inner = slice(n // 4, 3 * n // 4)
+        fig4[f"h{h}"] = {
+            "E_r_hdm": float(np.max(np.abs(dh - d)[inner])), "E_r_cdm": float(np.max(np.abs(dc - d)[inner])),
+            "Err_hdm": float(np.sqrt(np.mean((dh - d)[inner] ** 2))),
+            "Err_cdm": float(np.sqrt(np.mean((dc - d)[inner] ** 2))), "max_slope": float(d.max())}
+    out = {"kappa": kappa, "kappa_from": "T_r = 0.9 slab: 2 max W / max rho'^2", "slab_steps": slab_steps,
+           "droplet_steps": drop_steps, "rows": rows, "exponent_sigma_S": expo(sig_s), "exponent_sigma_L": expo(sig_l),
+           "exponent_paper": 1.49, "fig4": fig4}
+    print(f"[bench] surface tension: kappa {kappa:.4g}, exponents S {out['exponent_sigma_S']} L {out['exponent_sigma_L']}",
+          file=sys.stderr, flush=True)
+    del bs, bd
+    return out
+
+
 def adjoint_cost(steps: int, every: int, seed: int = 2024):
     """The differentiation workload: 256 x 256 CS droplet R = 48 (W = 4) at
     T = 0.7 Tc, FP64, tau = 1, SC + HDM; J = sum (rho_n - rho_target)^2 with
     the target from the same setup at g = 1.02.  Reports the adjoint step time
     over the forward step time, the whole-gradient time over the forward
-    rollout time, and peak device memory of the checkpointed gradient."""
+    rollout time (host clock around the backward; the bound set by the device
+    time of the recorded and reverse steps beside it), and peak device memory
+    of the checkpointed gradient."""
     import torch
 
     import paper_1712_06079_amd as L
@@ -383,19 +485,28 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats()
     base = torch.cuda.memory_allocated()
-    r0 = rho0.clone().requires_grad_(True)
-    g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
-    T = torch.tensor(p.T, dtype=torch.float64, requires_grad=True)
-    ev[2].record()
-    rho = rollout(r0, g, T, p, steps, every)
-    ev[3].record()
-    torch.cuda.synchronize()
-    t_roll = ev[2].elapsed_time(ev[3])
-    w0 = time.perf_counter()
-    J = ((rho - target) ** 2).sum()
-    J.backward()
-    torch.cuda.synchronize()
-    t_back = (time.perf_counter() - w0) * 1e3
+
+    def gradient():
+        r0 = rho0.clone().requires_grad_(True)
+        g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        T = torch.tensor(p.T, dtype=torch.float64, requires_grad=True)
+        ev[2].record()
+        rho = rollout(r0, g, T, p, steps, every)
+        ev[3].record()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        J = ((rho - target) ** 2).sum()
+        J.backward()
+        torch.cuda.synchronize()
+        return ev[2].elapsed_time(ev[3]), (time.perf_counter() - w0) * 1e3, J, g, T
+
+    # The first gradient of a process also pays one-time costs outside the
+    # method: the caching allocator's first hipMalloc of the checkpoint and
+    # segment buffers and the autograd engine's first use (loading torch's
+    # kernels for the objective's backward): about 0.3 s.  It is reported, and
+    # the second gradient is timed.
+    t_roll0, t_back0, _, _, _ = gradient()
+    t_roll, t_back, J, g, T = gradient()
     peak = torch.cuda.max_memory_allocated() - base
     return {
         "workload": "256x256 CS T=0.7Tc SC+HDM droplet R=48, J = |rho_n - rho(g=1.02)|^2",
@@ -403,7 +514,9 @@ def adjoint_cost(steps: int, every: int, seed: int = 2024):
         "ms_adjoint_step": round(t_adj, 5), "adjoint_over_forward": round(t_adj / t_fwd, 3),
         "ms_adjoint_step_single_call": round(t_adj1, 5), "ms_record_step": round(t_rec, 5),
         "ms_forward_rollout": round(t_roll, 2), "ms_backward": round(t_back, 2),
-        "gradient_over_forward": round((t_roll + t_back) / t_roll, 3), "peak_mib": round(peak / 2 ** 20, 1),
+        "gradient_over_forward": round((t_roll + t_back) / t_roll, 3),
+        "first_call": {"ms_forward_rollout": round(t_roll0, 2), "ms_backward": round(t_back0, 2)},
+        "device_bound_ratio": round((t_roll + steps * (t_rec + t_adj)) / t_roll, 3), "peak_mib": round(peak / 2 ** 20, 1),
         "J": float(J.item()), "dJ_dg": float(g.grad.item()), "dJ_dT": float(T.grad.item()),
     }
 
@@ -728,6 +841,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
     ap.add_argument("--fig5-steps", type=int, default=60000, help="steps of the coexistence comparison (0 = skip)")
+    ap.add_argument("--no-sigma", dest="sigma", action="store_false", help="skip the surface-tension report")
     ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
     ap.add_argument("--long-steps", type=int, default=50000, help="FP32-vs-FP64 large-case steps (0 = skip)")
     ap.add_argument("--curve-steps", type=int, default=200, help="steps per point of the size curve (0 = skip)")
@@ -777,6 +891,7 @@ def main():
         print(f"[bench] batch: {batch['domain_steps_per_s']:.0f} domain-steps/s batched, "
               f"{batch['domain_steps_per_s_separate']:.0f} separate", file=sys.stderr, flush=True)
     fig5 = fig5_coexistence(args.fig5_steps) if args.fig5_steps > 0 else None
+    sigma = surface_tension_report() if args.sigma else None
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_cost(args.adjoint_steps, 70)
@@ -816,6 +931,8 @@ def main():
         line["batch"] = batch
     if fig5:
         line["fig5_coexistence"] = fig5
+    if sigma:
+        line["surface_tension"] = sigma
     if adjoint:
         line["adjoint"] = adjoint
     if droplet:

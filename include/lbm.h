@@ -108,6 +108,30 @@ lbm_status lbm_maxwell(const lbm_params* p, double T, double* rho_v, double* rho
  * hold 40 doubles. */
 lbm_status lbm_hdm_row(int32_t n, int32_t prec, double* d, int32_t* taps);
 
+/* ---- flat interfaces (host, synchronous; host arrays) ----------------------
+ * The square-gradient fluid of Sec. 5.1 Eq. 25 (constant kappa, the k-scaled
+ * EOS p_m = k p_EOS of p's eos, a, b, R, omega at temperature p->T; k = p->k).
+ * In a flat interface Eq. 26 keeps P_yy = p_m - kappa rho rho'' +
+ * (kappa/2) rho'^2 equal to the coexistence pressure, whose first integral is
+ * (kappa/2) rho'^2 = W(rho) = rho * integral_{rho_b}^{rho} (p_m(s) - k p0)/s^2 ds
+ * (rho_b either Maxwell density, p0 the Maxwell pressure).  LBM_EINVAL for
+ * bad arguments or no coexistence at T. */
+
+/* W(rho[i]) for n densities (each inside (0, pole)). */
+lbm_status lbm_interface_excess(const lbm_params* p, int32_t n, const double* rho, double* W);
+
+/* The "exact" equilibrium profile of Sec. 5.1: rho and rho' at
+ * y_i = (i - (n - 1)/2) h, i < n, for the interface rising with y through the
+ * mean of the Maxwell densities at y = 0 (kappa > 0, h > 0). */
+lbm_status lbm_flat_profile(const lbm_params* p, double kappa, double h, int32_t n, double* rho, double* drho);
+
+/* Surface tension by the integration method of Sec. 5.3 with the tensor of
+ * Eq. 25, sigma = integral (P_N - P_T) dy = kappa integral rho'^2 dy, for one
+ * interface of a slab: rho is a periodic density column of n >= 5 sites
+ * (h = 1, two interfaces), rho' is Eq. 20 along it (drho, nullable, receives
+ * it) and *sigma = (kappa/2) sum rho'^2. */
+lbm_status lbm_sigma_slab(double kappa, int32_t n, const double* rho, double* drho, double* sigma);
+
 /* Device workspace needed by one domain with these parameters (bytes): two
  * population buffers f[9] per site (Sec. 2, Eqs. 1-3; FP64 or FP32 storage),
  * two planes of the potential field (Phi of Eq. 21 signed, or U of Eq. 8),

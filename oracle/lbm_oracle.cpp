@@ -802,7 +802,7 @@ void orc_collide_cell(const double* f9, double Fx, double Fy, double tau, double
 // "Exact" flat-interface profile of Sec. 5.1 (Eqs. 25-26): rho and rho' at
 // y_i = (i - (n - 1)/2) h, i < n, for the interface rising with y through
 // rho(0) = (rho_v + rho_l)/2.  Classic fourth-order Runge-Kutta on
-// rho' = sqrt(2 W(rho) / kappa) from y = 0 outwards, steps of at most h/16.
+// rho' = sqrt(2 W(rho) / kappa) from y = 0 outwards, steps of at most h/32.
 int orc_flat_profile(const orc_params* p, double kappa, double h, int n, double* rho, double* drho) {
     Interface f;
     if (!(kappa > 0.0) || !(h > 0.0) || n < 1 || !make_interface(*p, &f)) return 1;
@@ -813,7 +813,7 @@ int orc_flat_profile(const orc_params* p, double kappa, double h, int n, double*
         // grid points on this side, nearest first (y = 0 itself on the upper side)
         for (int i = (dir > 0) ? (int)std::ceil(c) : (int)std::ceil(c) - 1; i >= 0 && i < n; i += dir) {
             const double yt = (i - c) * h;
-            const int m = (int)std::ceil(std::fabs(yt - y) / (h / 16.0));
+            const int m = (int)std::ceil(std::fabs(yt - y) / (h / 32.0));
             const double dy = (m > 0) ? (yt - y) / m : 0.0;
             for (int s = 0; s < m; ++s) {
                 const double k1 = F(r), k2 = F(r + 0.5 * dy * k1), k3 = F(r + 0.5 * dy * k2), k4 = F(r + dy * k3);

@@ -12,8 +12,8 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
-__all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxwell", "hdm_row", "stream_probe", "EOS",
-           "FORCE", "GRAD", "PREC"]
+__all__ = ["Params", "Domain", "Batch", "LBMError", "library", "critical", "maxwell", "hdm_row", "stream_probe",
+           "interface_excess", "flat_profile", "sigma_slab", "EOS", "FORCE", "GRAD", "PREC"]
 
 EOS = {"vdw": 0, "pr": 1, "cs": 2, "rk": 3, "rks": 4}
 FORCE = {"sc": 0, "zc": 1, "hybrid": 2}
@@ -95,6 +95,9 @@ def library():
         L.lbm_record.argtypes = [_VP, C.c_int64, _VP, C.c_size_t, _VP]
         L.lbm_adjoint_steps.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
         L.lbm_stream_probe.argtypes = [C.c_int32, _VP, _VP, C.c_size_t, C.c_int32, _VP]
+        L.lbm_interface_excess.argtypes = [P, C.c_int32, D, D]
+        L.lbm_flat_profile.argtypes = [P, C.c_double, C.c_double, C.c_int32, D, D]
+        L.lbm_sigma_slab.argtypes = [C.c_double, C.c_int32, D, D, D]
         L.lbm_adjoint_step_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
         L.lbm_adjoint_noalloc_max_bytes.argtypes = []
         L.lbm_adjoint_noalloc_max_bytes.restype = C.c_size_t
@@ -105,7 +108,7 @@ def library():
                    "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
                    "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps", "lbm_stream_probe",
-                   "lbm_adjoint_step_noalloc"):
+                   "lbm_adjoint_step_noalloc", "lbm_interface_excess", "lbm_flat_profile", "lbm_sigma_slab"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -151,6 +154,37 @@ def _stream(stream):
     torch = _torch()
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def interface_excess(p: Params, rho):
+    """W(rho) of the flat interface (lbm_interface_excess) for a 1D float64 numpy array."""
+    import numpy as np
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    W = np.empty_like(r)
+    check(library().lbm_interface_excess(C.byref(p.c()), len(r), _dptr(r), _dptr(W)))
+    return W
+
+
+def flat_profile(p: Params, kappa: float, h: float, n: int):
+    """(y, rho, rho') of the exact flat-interface profile (lbm_flat_profile)."""
+    import numpy as np
+    rho, drho = np.empty(n), np.empty(n)
+    check(library().lbm_flat_profile(C.byref(p.c()), kappa, h, n, _dptr(rho), _dptr(drho)))
+    return (np.arange(n) - 0.5 * (n - 1)) * h, rho, drho
+
+
+def sigma_slab(kappa: float, column):
+    """(sigma, D rho) of one interface of a periodic slab column (lbm_sigma_slab)."""
+    import numpy as np
+    r = np.ascontiguousarray(column, dtype=np.float64)
+    d = np.empty_like(r)
+    s = C.c_double()
+    check(library().lbm_sigma_slab(kappa, len(r), _dptr(r), _dptr(d), C.byref(s)))
+    return s.value, d
 
 
 PROBE_KINDS = {"copy": 0, "read": 1, "write": 2}

@@ -19,9 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm_hip.so")
 HIP_SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_probe.hip"]
-HOST_SOURCES = ["eos_host.cpp", "hdm_coeffs.cpp"]
+HOST_SOURCES = ["eos_host.cpp", "hdm_coeffs.cpp", "interface_host.cpp"]
 SOURCES = HIP_SOURCES + HOST_SOURCES
-HEADERS = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_fused.hpp", "lbm_march.hpp", "lbm_adjoint.hpp", "lbm_internal.hpp", "eos_host.hpp", "hdm_coeffs.hpp"]
+HEADERS = ["lbm_device.hpp", "lbm_kernels.hpp", "lbm_fused.hpp", "lbm_march.hpp", "lbm_adjoint.hpp", "lbm_internal.hpp", "eos_host.hpp", "hdm_coeffs.hpp", "interface_host.hpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_NOTE = "'-packed-fp32-ops' is not a recognized feature for this target"

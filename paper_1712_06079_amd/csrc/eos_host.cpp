@@ -111,6 +111,8 @@ bool first_root(F fn, double rmax, double* root) {
 
 double eos_rho_max(const EosConst& e) { return (e.kind == EOS_CS) ? 4.0 / e.b : 1.0 / e.b; }
 
+double eos_psi(const EosConst& e, double rho, double T, double alpha) { return psi_integral(e, rho, T, alpha); }
+
 Jet eos_pressure(const EosConst& e, double rho, double T, double alpha) {
     Jet r{rho, 1.0, 0.0};
     return T * repulsive(e, r) - alpha * attractive(e, r);

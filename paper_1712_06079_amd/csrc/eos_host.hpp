@@ -36,4 +36,7 @@ bool eos_maxwell(const EosConst& e, double T, double* rho_v, double* rho_l, doub
 // Largest admissible density (pole of the repulsive term).
 double eos_rho_max(const EosConst& e);
 
+// Psi(rho) = integral of p / rho^2 d rho (closed form, up to a constant).
+double eos_psi(const EosConst& e, double rho, double T, double alpha);
+
 }  // namespace lbm_host

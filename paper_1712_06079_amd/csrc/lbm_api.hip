@@ -14,6 +14,7 @@
 #include "../../include/lbm.h"
 #include "eos_host.hpp"
 #include "hdm_coeffs.hpp"
+#include "interface_host.hpp"
 #include "lbm_adjoint.hpp"
 #include "lbm_fused.hpp"
 #include "lbm_march.hpp"
@@ -253,6 +254,35 @@ lbm_status lbm_hdm_row(int32_t n, int32_t prec, double* d, int32_t* taps) {
     *taps = lbm_host::hdm_taps(n, radius);
     for (int j = 0; j < lbm::JCAP; ++j) d[j] = 0.0;
     lbm_host::hdm_row(n, *taps, d);
+    return LBM_OK;
+}
+
+lbm_status lbm_interface_excess(const lbm_params* p, int32_t n, const double* rho, double* W) {
+    if (!p || !rho || !W || n < 0) return fail(LBM_EINVAL, "invalid arguments");
+    if (p->eos < 0 || p->eos > 4) return fail(LBM_EINVAL, "unknown eos %d", p->eos);
+    lbm_host::FlatInterface f;
+    if (!lbm_host::flat_interface(eos_const(p), p->T, p->k, &f))
+        return fail(LBM_EINVAL, "no liquid-vapour coexistence at T = %g (or k <= 0)", p->T);
+    for (int i = 0; i < n; ++i) {
+        if (!(rho[i] > 0.0) || !(rho[i] < lbm_host::eos_rho_max(f.e))) return fail(LBM_EINVAL, "density %g outside the EOS", rho[i]);
+        W[i] = lbm_host::interface_excess(f, rho[i]);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_flat_profile(const lbm_params* p, double kappa, double h, int32_t n, double* rho, double* drho) {
+    if (!p || !rho || !drho || n < 1 || !(kappa > 0.0) || !(h > 0.0)) return fail(LBM_EINVAL, "invalid arguments");
+    if (p->eos < 0 || p->eos > 4) return fail(LBM_EINVAL, "unknown eos %d", p->eos);
+    lbm_host::FlatInterface f;
+    if (!lbm_host::flat_interface(eos_const(p), p->T, p->k, &f))
+        return fail(LBM_EINVAL, "no liquid-vapour coexistence at T = %g (or k <= 0)", p->T);
+    lbm_host::flat_profile(f, kappa, h, n, rho, drho);
+    return LBM_OK;
+}
+
+lbm_status lbm_sigma_slab(double kappa, int32_t n, const double* rho, double* drho, double* sigma) {
+    if (!rho || !sigma || n < 5 || !(kappa > 0.0)) return fail(LBM_EINVAL, "invalid arguments");
+    *sigma = lbm_host::sigma_slab(kappa, n, rho, drho);
     return LBM_OK;
 }
 

@@ -396,3 +396,19 @@ def test_largest_lattice_properties(prec):
     assert abs(m["totals"][0].item() / m0 - 1) < (1e-13 if prec == "f64" else 1e-6)
     del d, rho, m, rho0
     torch.cuda.empty_cache()
+
+
+def test_sigma_from_gpu_slab():
+    """Sec. 5.3's integration method on a simulated flat interface: the GPU
+    supplies the slab (van der Waals, T_r = 0.7, 8 x 128, 3000 steps), the
+    library's sigma_S of its density column equals the oracle's sigma_S of the
+    oracle's own slab, and both columns agree."""
+    po = PINS.c1_params(nx=8, ny=128, T=0.7 * VDW_TC)
+    rv, rl, _ = O.maxwell(po, po.T)
+    rho0 = I.slab(8, 128, rv, rl, 5.0, axis="y")
+    got = gpu_run(po, rho0, 3000)["rho"].mean(axis=1)
+    ref = oracle_run(po, rho0, 3000)["rho"].mean(axis=1)
+    assert rel_err(got, ref) < 1e-12
+    kappa = 0.01
+    s_gpu, _ = L.sigma_slab(kappa, got)
+    assert abs(s_gpu / O.sigma_slab(kappa, ref) - 1) < 1e-11

@@ -108,3 +108,41 @@ def test_rollout_rejects_bad_schedule(nsteps, every):
     from paper_1712_06079_amd.autograd import _check_schedule
     with pytest.raises(ValueError):
         _check_schedule(nsteps, every)
+
+
+@pytest.mark.parametrize("kind,tr,kappa", [("vdw", 0.9, 0.004), ("vdw", 0.6, 0.02), ("cs", 0.7, 0.05), ("pr", 0.8, 0.01),
+                                           ("rks", 0.75, 0.005)])
+def test_flat_profile_matches_oracle(kind, tr, kappa):
+    """The exact flat-interface profile of Eqs. 25-26 (library: closed-form W,
+    Runge-Kutta steps of h/64; oracle: W by quadrature, steps of h/32) agree to
+    the integration error (the densities within 1e-6 relative, the slopes within
+    1e-6 of the steepest) on interfaces a few lattice units wide."""
+    po = PINS.eos_params(kind)
+    tc, _ = O.critical(po)
+    po.T = tr * tc
+    p = L.Params(eos=kind, a=po.a, b=po.b, R=po.R, omega=po.omega, k=po.k, T=po.T)
+    _, r, d = L.flat_profile(p, kappa, 0.5, 121)
+    _, r2, d2 = O.flat_profile(po, kappa, 0.5, 121)
+    assert np.max(np.abs(r - r2) / r2) < 1e-6
+    assert np.max(np.abs(d - d2)) < 1e-6 * d2.max()
+
+
+def test_sigma_slab_matches_oracle():
+    """Integration-method surface tension of a periodic slab column (Eq. 20
+    derivative): library and oracle within rounding, for a short column (whole
+    periodic row) and a long one (truncated row)."""
+    rng = np.random.default_rng(31)
+    for n in (40, 256):
+        col = 2.0 + np.sin(2 * np.pi * np.arange(n) / n) + 0.1 * rng.standard_normal(n)
+        s, d = L.sigma_slab(0.01, col)
+        assert abs(s / O.sigma_slab(0.01, col) - 1) < 1e-13
+        assert np.max(np.abs(d - O.hdm_line(col))) < 1e-14 * np.abs(O.hdm_line(col)).max()
+
+
+def test_flat_interface_rejects_bad_input():
+    p = L.Params(eos="vdw", T=0.6, k=0.01)  # T > Tc = 4/7
+    with pytest.raises(L.LBMError):
+        L.flat_profile(p, 0.01, 0.5, 11)
+    p.T = 0.5
+    with pytest.raises(L.LBMError):
+        L.flat_profile(p, -1.0, 0.5, 11)
