@@ -27,6 +27,11 @@
 //    use is dimension by dimension: d/dx along each row, d/dy along each column.
 //  * Eq. 15 as printed lacks the factor 1/c_s^2 = 3 (its sum is c_s^2 grad u);
 //    the factor is applied.
+//  * Walls (Sec. 5.5 states no-slip walls in y but neither the scheme nor a
+//    closure of Eq. 20): halfway bounce-back puts the wall midway between the
+//    last fluid row and the next; the potential is continued past the wall by
+//    its mirror image (zero normal derivative: a neutral wall), which gives
+//    Eq. 20 two closure rows at each end (below).
 //  * Eq. 29 (Carnahan-Starling) prints the denominator as (1 - (b rho/4)^3);
 //    the Carnahan-Starling form (1 - b rho/4)^3 is used.
 //  * Hu's scaling p_m = k p_EOS (Sec. 5) enters U = g (k p_EOS - rho c_s^2).
@@ -56,7 +61,8 @@ typedef struct {
     int32_t force;  // 0 Shan-Chen (Eq. 22), 1 Zhang-Chen (Eq. 7), 2 hybrid (Eq. 9)
     int32_t grad;   // 0 high-order difference (Eq. 20), 1 central difference (Eq. 14),
                     // 2 weighted D2Q9 central difference (Eq. 15, with the 1/c_s^2 factor)
-    int32_t pad_;
+    int32_t walls;  // 0 periodic in y; 1 no-slip walls at y = -1/2 and ny - 1/2 (halfway
+                    // bounce-back; the potential mirrored at the wall for the gradient)
     double tau;     // relaxation time (Eq. 1)
     double a, b, R, omega;  // EOS constants; omega = acentric factor (PR, RKS)
     double T;       // absolute temperature
@@ -466,6 +472,36 @@ void hdm_line(int n, const S* u, long su, S* y, long sy) {
     for (int i = 0; i < n; ++i) y[i * sy] = x[i] - fact * z[i];
 }
 
+// Eq. 20 on a line of n points between two walls (halfway, at -1/2 and
+// n - 1/2) with the mirror continuation u_{-1-j} = u_j, u_{n+j} = u_{n-1-j};
+// the derivative of such an even continuation is odd: y'_{-1} = -y'_0,
+// y'_n = -y'_{n-1}.  Substituting both into the first and last rows of Eq. 20
+// leaves a plain tridiagonal system with diagonal 2/3 in those two rows, solved
+// by the chasing method.
+inline int mirror_index(int j, int n) { return j < 0 ? -1 - j : (j >= n ? 2 * n - 1 - j : j); }
+
+template <typename S>
+void hdm_line_walls(int n, const S* u, long su, S* y, long sy) {
+    const double third = 1.0 / 3.0;
+    std::vector<S> rhs(n), x(n);
+    for (int i = 0; i < n; ++i) {
+        S up2 = u[mirror_index(i + 2, n) * su], um2 = u[mirror_index(i - 2, n) * su];
+        S up1 = u[mirror_index(i + 1, n) * su], um1 = u[mirror_index(i - 1, n) * su];
+        rhs[i] = (up2 - um2) / 36.0 + 7.0 * (up1 - um1) / 9.0;
+    }
+    std::vector<double> sub(n, third), diag(n, 1.0), sup(n, third);
+    diag[0] -= third;
+    diag[n - 1] -= third;
+    thomas<S>(n, sub.data(), diag.data(), sup.data(), rhs.data(), x.data());
+    for (int i = 0; i < n; ++i) y[i * sy] = x[i];
+}
+
+// Eq. 14 between two walls: the same mirror continuation.
+template <typename S>
+void cdm_line_walls(int n, const S* u, long su, S* y, long sy) {
+    for (int i = 0; i < n; ++i) y[i * sy] = (u[mirror_index(i + 1, n) * su] - u[mirror_index(i - 1, n) * su]) / 2.0;
+}
+
 // Central difference, Eq. 14 with h = 1, periodic.
 template <typename S>
 void cdm_line(int n, const S* u, long su, S* y, long sy) {
@@ -502,13 +538,20 @@ void d2q9_derivative(int axis, int nx, int ny, const S* u, S* out) {
 // d/dx (axis 0) or d/dy (axis 1) of the field u [ny][nx] with the gradient
 // scheme `grad`: 0 Eq. 20 and 1 Eq. 14, each along its own grid lines (d/dx
 // along every row, d/dy along every column); 2 the two-dimensional Eq. 15.
+// With walls (y only, grads 0 and 1) the y lines use the mirror closure.
 template <typename S>
-void derivative(int grad, int axis, int nx, int ny, const S* u, S* out) {
+void derivative(int grad, int axis, int nx, int ny, const S* u, S* out, int walls = 0) {
     if (grad == 2) {
         d2q9_derivative<S>(axis, nx, ny, u, out);
     } else if (axis == 0) {
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) derivative_line<S>(grad, nx, &u[(size_t)y * nx], 1, &out[(size_t)y * nx], 1);
+    } else if (walls) {
+#pragma omp parallel for schedule(static)
+        for (int x = 0; x < nx; ++x) {
+            if (grad == 1) cdm_line_walls<S>(ny, &u[x], nx, &out[x], nx);
+            else hdm_line_walls<S>(ny, &u[x], nx, &out[x], nx);
+        }
     } else {
 #pragma omp parallel for schedule(static)
         for (int x = 0; x < nx; ++x) derivative_line<S>(grad, ny, &u[x], nx, &out[x], nx);
@@ -576,11 +619,11 @@ void forces(const Model& m, const S* f, S T, S g, Work<S>& w) {
     const bool need_U = (m.p.force == 1 || m.p.force == 2);
     if (need_phi) {
         derivative<S>(m.p.grad, 0, nx, ny, w.phi.data(), w.gx.data());
-        derivative<S>(m.p.grad, 1, nx, ny, w.phi.data(), w.gy.data());
+        derivative<S>(m.p.grad, 1, nx, ny, w.phi.data(), w.gy.data(), m.p.walls);
     }
     if (need_U) {
         derivative<S>(m.p.grad, 0, nx, ny, w.U.data(), w.gux.data());
-        derivative<S>(m.p.grad, 1, nx, ny, w.U.data(), w.guy.data());
+        derivative<S>(m.p.grad, 1, nx, ny, w.U.data(), w.guy.data(), m.p.walls);
     }
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < (long)N; ++c) {
@@ -620,8 +663,18 @@ void collide_cell(const S* fi, S rho, S jx, S jy, S Fx, S Fy, double tau, S* out
     }
 }
 
+// Opposite D2Q9 direction.
+int opposite(int i) {
+    for (int j = 0; j < 9; ++j)
+        if (EX[j] == -EX[i] && EY[j] == -EY[i]) return j;
+    return i;
+}
+
 // One full time step f_t -> f_{t+1} (Eq. 1): collide everywhere, then stream
-// f_i(x + e_i) <- f*_i(x) with periodic wrap.  Layout f[i][y][x].
+// f_i(x + e_i) <- f*_i(x) with periodic wrap (in x always; in y unless there
+// are walls).  With walls a population whose step would cross y = -1/2 or
+// ny - 1/2 returns to its own site reversed (halfway bounce-back, no slip).
+// Layout f[i][y][x].
 template <typename S>
 void step(const Model& m, const S* f, S* fout, S T, S g, Work<S>& w) {
     const int nx = m.p.nx, ny = m.p.ny;
@@ -635,6 +688,10 @@ void step(const Model& m, const S* f, S* fout, S T, S g, Work<S>& w) {
             for (int i = 0; i < 9; ++i) fi[i] = f[i * N + c];
             collide_cell<S>(fi, w.rho[c], w.jx[c], w.jy[c], w.Fx[c], w.Fy[c], m.p.tau, fs);
             for (int i = 0; i < 9; ++i) {
+                if (m.p.walls && (y + EY[i] < 0 || y + EY[i] >= ny)) {
+                    fout[opposite(i) * N + c] = fs[i];
+                    continue;
+                }
                 int xd = (x + EX[i] + nx) % nx, yd = (y + EY[i] + ny) % ny;
                 fout[i * N + (size_t)yd * nx + xd] = fs[i];
             }
@@ -778,12 +835,14 @@ void orc_eos(const orc_params* p, double rho, double T, double* pe, double* dp, 
 }
 
 void orc_hdm_line(int n, const double* u, double* du) { hdm_line<double>(n, u, 1, du, 1); }
+void orc_hdm_line_walls(int n, const double* u, double* du) { hdm_line_walls<double>(n, u, 1, du, 1); }
+void orc_cdm_line_walls(int n, const double* u, double* du) { cdm_line_walls<double>(n, u, 1, du, 1); }
 
 // Both derivatives of a field u [ny][nx] with the scheme p->grad (the step's
 // gradient operator, Sec. 3): gx = d/dx, gy = d/dy.
 void orc_gradient(const orc_params* p, const double* u, double* gx, double* gy) {
     derivative<double>(p->grad, 0, p->nx, p->ny, u, gx);
-    derivative<double>(p->grad, 1, p->nx, p->ny, u, gy);
+    derivative<double>(p->grad, 1, p->nx, p->ny, u, gy, p->walls);
 }
 void orc_cdm_line(int n, const double* u, double* du) { cdm_line<double>(n, u, 1, du, 1); }
 
@@ -921,7 +980,7 @@ int orc_tangent_run(const orc_params* p, int64_t nsteps, double* f, double* df, 
 // Reverse mode of one step: lam = (d f_{t+1} / d f_t)^T lam_next for the state f
 // (= f_t), and grad[0] += dJ/dg, grad[1] += dJ/dT.  Layouts [9][ny][nx].
 int orc_adjoint_step(const orc_params* p, const double* f, const double* lam_next, double* lam, double* grad) {
-    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5)) return 1;
+    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5) || p->walls) return 1;
     Model m = make_model(*p);
     adjoint_step(m, f, lam_next, lam, grad);
     return 0;
@@ -934,7 +993,7 @@ int orc_adjoint_step(const orc_params* p, const double* f, const double* lam_nex
 int orc_adjoint_run(const orc_params* p, int64_t nsteps, int64_t every, const double* rho0, const double* ux0,
                     const double* uy0, const double* target, double* J, double* dJ_df0, double* dJ_drho0,
                     double* grad) {
-    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5) || every < 1) return 1;
+    if (p->nx < 5 || p->ny < 5 || !(p->tau > 0.5) || every < 1 || p->walls) return 1;
     Model m = make_model(*p);
     const size_t N = (size_t)p->nx * p->ny;
     std::vector<double> f0(9 * N);

@@ -21,7 +21,7 @@ EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 class _P(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("eos", C.c_int32), ("force", C.c_int32),
-                ("grad", C.c_int32), ("pad_", C.c_int32), ("tau", C.c_double), ("a", C.c_double),
+                ("grad", C.c_int32), ("walls", C.c_int32), ("tau", C.c_double), ("a", C.c_double),
                 ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double), ("T", C.c_double),
                 ("k", C.c_double), ("g", C.c_double), ("A", C.c_double)]
 
@@ -42,9 +42,10 @@ class Params:
     k: float = 0.01
     g: float = 1.0
     A: float = 0.0
+    walls: int = 0
 
     def c(self) -> _P:
-        return _P(self.nx, self.ny, EOS[self.eos], FORCE[self.force], GRAD[self.grad], 0,
+        return _P(self.nx, self.ny, EOS[self.eos], FORCE[self.force], GRAD[self.grad], int(self.walls),
                   self.tau, self.a, self.b, self.R, self.omega, self.T, self.k, self.g, self.A)
 
 
@@ -61,6 +62,8 @@ def load(path: str):
     L.orc_hdm_line.argtypes = [C.c_int, _D, _D]
     L.orc_cdm_line.argtypes = [C.c_int, _D, _D]
     L.orc_gradient.argtypes = [P, _D, _D, _D]
+    L.orc_hdm_line_walls.argtypes = [C.c_int, _D, _D]
+    L.orc_cdm_line_walls.argtypes = [C.c_int, _D, _D]
     L.orc_flat_profile.argtypes = [P, C.c_double, C.c_double, C.c_int, _D, _D]
     L.orc_flat_profile.restype = C.c_int
     L.orc_sigma_slab.argtypes = [C.c_double, C.c_int, _D]
@@ -178,6 +181,22 @@ def sigma_exact(p: Params, kappa: float):
     if lib().orc_sigma_exact(C.byref(p.c()), kappa, C.byref(s)):
         raise ValueError("no flat interface for these parameters")
     return s.value
+
+
+def hdm_line_walls(u):
+    """Eq. 20 on a line between two walls (mirror closure)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().orc_hdm_line_walls(len(u), _ptr(u), _ptr(out))
+    return out
+
+
+def cdm_line_walls(u):
+    """Eq. 14 on a line between two walls (mirror closure)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().orc_cdm_line_walls(len(u), _ptr(u), _ptr(out))
+    return out
 
 
 def feq(rho, ux, uy):

@@ -627,6 +627,105 @@ def pin_adjoint_checkpoint_invariance():
     assert a["dg"] == b["dg"] == c["dg"] and a["dT"] == b["dT"] == c["dT"]
 
 
+# ------------------------------------------------------------------ walls (Sec. 5.5)
+def pin_wall_closure_modes():
+    """The mirror closure of Eq. 20 (and Eq. 14) between walls at -1/2 and
+    n - 1/2: u_j = cos(theta (j + 1/2)), theta = pi m / n, continues past both
+    walls into a Fourier mode of period 2n, so its derivative must be exactly
+    -k'(theta) sin(theta (j + 1/2)) (k' the Eq. 20 symbol; sin theta for Eq. 14)
+    for every m, including the rows next to the walls."""
+    for n in (5, 6, 9, 16, 31):
+        j = np.arange(n)
+        for m in range(n):
+            th = np.pi * m / n
+            u = np.cos(th * (j + 0.5))
+            s = np.sin(th * (j + 0.5))
+            assert np.max(np.abs(O.hdm_line_walls(u) + hdm_symbol(th) * s)) < 2e-13, (n, m)
+            assert np.max(np.abs(O.cdm_line_walls(u) + np.sin(th) * s)) < 1e-13, (n, m)
+
+
+def pin_wall_tanh_film():
+    """The tanh test of Eqs. 16-18 next to a wall: a film rho = 1 - tanh(2(y - a)/W)
+    on the lower wall (a = 4W from it) with the upper wall far away.  Against
+    the exact derivative the closure keeps the interior accuracy of the
+    periodic line (within a factor 1.5 of the same profile on a periodic line)
+    and the high-order difference stays far more accurate than Eq. 14."""
+    for W in (3.0, 5.0):
+        n, a = 160, 4 * W
+        y = np.arange(n, dtype=float)
+        rho = 1 - np.tanh(2 * (y - a) / W)
+        exact = -(2 / W) / np.cosh(2 * (y - a) / W) ** 2
+        eh = np.sqrt(np.mean((O.hdm_line_walls(rho) - exact) ** 2))
+        ec = np.sqrt(np.mean((O.cdm_line_walls(rho) - exact) ** 2))
+        per = 1 - np.tanh(2 * (y - n / 4) / W) + np.tanh(2 * (y - 3 * n / 4) / W)
+        exp_ = -(2 / W) / np.cosh(2 * (y - n / 4) / W) ** 2 + (2 / W) / np.cosh(2 * (y - 3 * n / 4) / W) ** 2
+        ep = np.sqrt(np.mean((O.hdm_line(per) - exp_) ** 2)) / np.sqrt(2.0)  # two interfaces there
+        assert eh < 1.5 * ep and eh < ec / 4, (W, eh, ep, ec)
+
+
+def _channel(ny=40, nx=5, **kw):
+    p = c1_params(nx=nx, ny=ny, walls=1, **kw)
+    return p
+
+
+def pin_walls_conserve_and_rest():
+    """With walls, a uniform fluid at rest stays at rest (every population of
+    every row unchanged to rounding) and a droplet by the wall keeps its mass
+    to rounding over 300 steps (bounce-back returns every population)."""
+    p = _channel(ny=16, nx=8)
+    f0 = O.init(p, np.full((16, 8), 2.5))
+    f1 = O.run(p, f0, 50)
+    assert np.max(np.abs(f1 - f0)) < 1e-15
+    p = _channel(ny=30, nx=24)
+    rv, rl, _ = O.maxwell(p, p.T)
+    rho0 = I.droplet(24, 30, rv, rl, 7.0, 4.0, cx=12.0, cy=6.0, noise=1e-3, seed=3)
+    f0 = O.init(p, rho0)
+    f1 = O.run(p, f0, 300)
+    assert abs(f1.sum() / f0.sum() - 1) < 1e-13
+
+
+def pin_channel_shear_decay():
+    """No slip: without force the lowest shear mode between halfway walls,
+    u_x = u0 sin(pi (y + 1/2) / N), decays as exp(-nu (pi/N)^2 t) with
+    nu = (2 tau - 1)/6 (a free-slip wall would let the mode cos(...) of zero
+    rate survive instead)."""
+    N = 32
+    y = np.arange(N)
+    mode = np.sin(np.pi * (y + 0.5) / N)
+    for tau, tol in ((1.0, 2e-3), (0.8, 5e-3)):
+        p = _channel(ny=N, nx=5, tau=tau, g=0.0)
+        u0 = 1e-3
+        ux = np.repeat((u0 * mode)[:, None], 5, axis=1)
+        f = O.run(p, O.init(p, np.ones((N, 5)), ux, np.zeros((N, 5))), 600)
+        vx = O.moments(p, f)["vx"][:, 0]
+        amp = np.sum(vx * mode) / np.sum(mode * mode)
+        nu = (2 * tau - 1) / 6
+        want = np.exp(-nu * (np.pi / N) ** 2 * 600)
+        assert abs(amp / u0 / want - 1) < tol, (tau, amp / u0, want)
+
+
+def pin_walls_equal_mirrored_slab():
+    """A flat liquid film on the lower wall of a channel of height n (no flow
+    along the wall) is the upper half of a periodic slab of height 2n holding
+    the film and its mirror image: bounce-back and specular reflection agree
+    on such states, and the mirror closure of Eq. 20 is Eq. 20 on the doubled
+    periodic line.  The two runs (closure rows against the cyclic solve) agree
+    to rounding after 400 steps, for SC and ZC."""
+    n = 40
+    for force in ("sc", "zc"):
+        pw = _channel(ny=n, nx=5, force=force)
+        rv, rl, _ = O.maxwell(pw, pw.T)
+        y = np.arange(n)
+        film = rv + 0.5 * (rl - rv) * (1 - np.tanh(2 * (y - 12.0) / 5.0))
+        fw = O.run(pw, O.init(pw, np.repeat(film[:, None], 5, axis=1)), 400)
+        pp = c1_params(nx=5, ny=2 * n, force=force)
+        per = np.concatenate([film[::-1], film])  # rows n .. 2n-1 hold the channel
+        fp = O.run(pp, O.init(pp, np.repeat(per[:, None], 5, axis=1)), 400)
+        rw = O.moments(pw, fw)["rho"][:, 0]
+        rp = O.moments(pp, fp)["rho"][n:, 0]
+        assert np.max(np.abs(rw - rp) / rp) < 1e-12, (force, np.max(np.abs(rw - rp) / rp))
+
+
 # ------------------------------------------------------------------ Sec. 5.1, Eqs. 25-26
 def pin_flat_profile_satisfies_eq26():
     """The exact flat-interface profile (VDW, T_r = 0.9, k = 0.01, two kappas)
@@ -715,5 +814,7 @@ FAST = [
     pin_flat_interface_equilibrium, pin_tangent_matches_differences, pin_adjoint_dot_product,
     pin_adjoint_finite_differences, pin_adjoint_checkpoint_invariance, pin_hybrid_limits,
     pin_flat_profile_satisfies_eq26, pin_integration_method_sigma, pin_sigma_critical_exponent,
+    pin_wall_closure_modes, pin_wall_tanh_film, pin_walls_conserve_and_rest, pin_channel_shear_decay,
+    pin_walls_equal_mirrored_slab,
 ]
 SLOW = [pin_maxwell_equal_area, pin_hdm_beats_cdm_coexistence, pin_table1_laplace]

@@ -84,6 +84,11 @@ MUTANTS = {
     "sigma_slab_both_interfaces": ("return 0.5 * kappa * sum;", "return kappa * sum;"),
     "sigma_exact_without_two": ("std::sqrt(2.0 * kappa * excess_W(f, c + 0.5 * hs * GL8_X[j]))",
                                 "std::sqrt(kappa * excess_W(f, c + 0.5 * hs * GL8_X[j]))"),
+    "wall_closure_rows": ("    diag[0] -= third;\n    diag[n - 1] -= third;\n", ""),
+    "wall_mirror_about_last_row": ("return j < 0 ? -1 - j : (j >= n ? 2 * n - 1 - j : j);", "return j < 0 ? -1 - j : (j >= n ? 2 * n - 2 - j : j);"),
+    "bounce_back_keeps_direction": ("fout[opposite(i) * N + c] = fs[i];", "fout[i * N + c] = fs[i];"),
+    "walls_ignored_in_force": ("derivative<S>(m.p.grad, 1, nx, ny, w.phi.data(), w.gy.data(), m.p.walls);",
+                               "derivative<S>(m.p.grad, 1, nx, ny, w.phi.data(), w.gy.data());"),
     # Eq. 9 weights, changed consistently in the forward force and its adjoint
     # (a mistake made in both passes survives the dot-product identity)
     "hybrid_sc_weight_both_passes": ("(1.0 - 2.0 * m.p.A)", "(1.0 - m.p.A)"),
@@ -126,13 +131,14 @@ def builds():
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(builds, name):
     prev = O.use(O.load(builds[name]))
-    caught = []
+    caught = None
     try:
         for pin in P.FAST:
             try:
                 pin()
             except (AssertionError, ValueError, FloatingPointError, ZeroDivisionError):
-                caught.append(pin.__name__)
+                caught = pin.__name__
+                break
     finally:
         O.use(prev)
     assert caught, f"no pin catches mutant {name}"
