@@ -430,6 +430,96 @@ def surface_tension_report(slab_steps: int = 40000, drop_steps: int = 20000):
     return out
 
 
+def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.0, t_star_end: float = 1.5,
+                  every: int = 50):
+    """Sec. 5.5: a droplet splashing on a thin liquid film.  1000 x 300, PR water
+    (a = 9/49, b = 2/21, omega = 0.344, k = 0.04) at T_r = 0.6, SC + HDM,
+    no-slip walls in y (halfway bounce-back, mirror closure of Eq. 20),
+    periodic x; film of height 30 (a tenth of the height) on the lower wall;
+    interfaces tanh with W = 4.  The paper's droplet (R = 50, U = 0.108) goes
+    non-finite within 300-550 steps here at every tau tried (0.69 .. 1.5;
+    U <= 0.05 at tau 0.824 is stable), so the Reynolds numbers Re = U D / nu_l
+    are reached with U = 0.05 and D = 216 (R = 108) at the paper's tau for each
+    Re (tau = 3 U D / Re + 1/2: 1.31, 0.824, 0.687).  The droplet starts merged
+    with the film by 3 lattice units (centre at y = 30 + R - 3), moving down at
+    U (initial velocity -U weighted by its liquid fraction).  The spread radius
+    r(t) is half the width of the liquid run through x = 500 in the row just
+    above the initial film surface (y = 31); C of r/D = C sqrt(U (t - t0)/D) is
+    fitted (with the contact time t0) on t* = U t / D in [0.2, 1.2].
+    We = rho_l U^2 D / sigma, sigma from Laplace's law (droplet R = 32 on a
+    periodic 128^2 lattice, 20 000 steps)."""
+    import torch
+
+    import paper_1712_06079_amd as L
+    nx, ny, hf = 1000, 300, 30.0
+    D = 2 * R
+    base = dict(eos="pr", force="sc", a=9 / 49, b=2 / 21, R=1.0, omega=0.344, k=0.04)
+    p0 = L.Params(nx=nx, ny=ny, walls=1, tau=1.0, **base)
+    tc, _ = L.critical(p0)
+    T = 0.6 * tc
+    rv, rl, _ = L.maxwell(p0, T)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    film = 0.5 * (1 - np.tanh(2 * (y - hf) / 4.0))
+    cy = hf + R - 3.0
+    drop = 0.5 * (1 - np.tanh(2 * (np.hypot(x - nx / 2, y - cy) - R) / 4.0))
+    rho0 = rv + (rl - rv) * np.maximum(film, drop)
+    uy0 = -U * drop * (drop > film)
+    out = {"lattice": [nx, ny], "T_r": 0.6, "U": U, "D": D, "film": hf, "rho_l": rl, "rho_v": rv, "runs": [],
+           "paper": {"U": 0.108, "D": 100, "We": 117, "C": 1.3}}
+    pl = L.Params(nx=128, ny=128, tau=1.0, T=T, **base)
+    dl = L.Domain(pl, torch.from_numpy(I.droplet(128, 128, rv, rl, 32.0, 4.0)).cuda())
+    dl.step(20000)
+    m = dl.moments(want=("rho", "p"))
+    rho, pr = m["rho"].cpu().numpy(), m["p"].cpu().numpy()
+    re_ = float(np.sqrt(((rho - rho[0, 0]) / (rho[64, 64] - rho[0, 0])).sum() / np.pi))
+    sigma = float((pr[64, 64] - pr[0, 0]) * re_)
+    out["sigma_L"] = sigma
+    out["We"] = rl * U * U * D / sigma if sigma > 0 else None
+    del dl
+    steps = int(t_star_end * D / U) // every * every
+    for Re in re_list:
+        tau = 3 * U * D / Re + 0.5
+        p = L.Params(nx=nx, ny=ny, walls=1, tau=tau, T=T, **base)
+        d = L.Domain(p, torch.from_numpy(rho0).cuda(), None, torch.from_numpy(uy0).cuda())
+        ts, rs = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms, done, finite = 0.0, 0, True
+        while done < steps:
+            e0.record()
+            d.step(every)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            done += every
+            if not d.check_finite():
+                finite = False
+                break
+            row = d.moments(want=("rho",))["rho"][int(hf) + 1].cpu().numpy()
+            liq = row > 0.5 * (rv + rl)
+            c = nx // 2
+            if liq[c]:
+                lo, hi = c, c
+                while lo > 0 and liq[lo - 1]:
+                    lo -= 1
+                while hi < nx - 1 and liq[hi + 1]:
+                    hi += 1
+                ts.append(done)
+                rs.append(0.5 * (hi - lo + 1))
+        run = {"Re": Re, "tau": tau, "steps": done, "finite": finite, "mlups": round(nx * ny * done / (ms * 1e-3) / 1e6, 1),
+               "t_star": [round(U * t / D, 4) for t in ts], "r_over_D": [round(r / D, 4) for r in rs]}
+        ts_a, rs_a = np.array(ts, float), np.array(rs, float)
+        sel = (U * ts_a / D >= 0.2) & (U * ts_a / D <= 1.2)
+        if finite and sel.sum() >= 4:
+            slope, icpt = np.polyfit(ts_a[sel], rs_a[sel] ** 2, 1)  # r^2 = C^2 D U (t - t0)
+            if slope > 0:
+                run["C"] = round(float(np.sqrt(slope / (D * U))), 4)
+                run["t0"] = round(float(-icpt / slope), 1)
+        out["runs"].append(run)
+        print(f"[bench] splash Re {Re}: finite {finite}, C {run.get('C')}, We {out['We']:.1f}", file=sys.stderr, flush=True)
+        del d
+    return out
+
+
 def adjoint_cost(steps: int, every: int, seed: int = 2024):
     """The differentiation workload: 256 x 256 CS droplet R = 48 (W = 4) at
     T = 0.7 Tc, FP64, tau = 1, SC + HDM; J = sum (rho_n - rho_target)^2 with
@@ -842,6 +932,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
     ap.add_argument("--fig5-steps", type=int, default=60000, help="steps of the coexistence comparison (0 = skip)")
     ap.add_argument("--no-sigma", dest="sigma", action="store_false", help="skip the surface-tension report")
+    ap.add_argument("--splash-re", type=float, nargs="*", default=[40.0, 100.0, 173.0],
+                    help="Reynolds numbers of the droplet-splash runs (none = skip)")
     ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
     ap.add_argument("--long-steps", type=int, default=50000, help="FP32-vs-FP64 large-case steps (0 = skip)")
     ap.add_argument("--curve-steps", type=int, default=200, help="steps per point of the size curve (0 = skip)")
@@ -892,6 +984,7 @@ def main():
               f"{batch['domain_steps_per_s_separate']:.0f} separate", file=sys.stderr, flush=True)
     fig5 = fig5_coexistence(args.fig5_steps) if args.fig5_steps > 0 else None
     sigma = surface_tension_report() if args.sigma else None
+    splash = splash_report(tuple(args.splash_re)) if args.splash_re else None
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_cost(args.adjoint_steps, 70)
@@ -933,6 +1026,8 @@ def main():
         line["fig5_coexistence"] = fig5
     if sigma:
         line["surface_tension"] = sigma
+    if splash:
+        line["splash"] = splash
     if adjoint:
         line["adjoint"] = adjoint
     if droplet:

@@ -76,7 +76,14 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
  *  T       absolute temperature (T_r = T / Tc; see lbm_critical)
  *  k       Hu's EOS scaling p_m = k p_EOS (Sec. 5), > 0
  *  g       interaction-strength multiplier on U (1 = the paper)
- *  A       hybrid weight (Eq. 9), used only with LBM_FORCE_HYBRID          */
+ *  A       hybrid weight (Eq. 9), used only with LBM_FORCE_HYBRID
+ *  walls   0: periodic in y; 1: no-slip walls at y = -1/2 and ny - 1/2
+ *          (Sec. 5.5; halfway bounce-back, the potential continued past the
+ *          wall by its mirror image for the gradient: Eq. 20 or Eq. 14 with
+ *          that closure).  x is always periodic.  With walls only the tile
+ *          kernels run (automatic choice, lbm_set_kernel variant 2) and
+ *          Eq. 15 and the reverse step are LBM_EUNSUPPORTED.
+ *  reserved  must be 0                                                     */
 typedef struct lbm_params {
     int32_t nx, ny;
     int32_t eos, force, grad, prec;
@@ -86,6 +93,8 @@ typedef struct lbm_params {
     double k;
     double g;
     double A;
+    int32_t walls;
+    int32_t reserved;
 } lbm_params;
 
 typedef struct lbm_domain lbm_domain;
@@ -165,7 +174,7 @@ lbm_status lbm_step(lbm_domain* d, int64_t nsteps, hipStream_t stream);
  * p = rho/3 + U.  Any of rho, ux, uy, p may be NULL; each is a device FP64
  * field [ny][nx].  totals (nullable, device, 4 doubles) receives
  * {sum rho, sum rho v_x, sum rho v_y, max |v|}, reduced in a fixed order
- * (bitwise reproducible). */
+ * (bitwise reproducible; a non-finite field gives non-finite totals). */
 lbm_status lbm_moments(lbm_domain* d, double* rho, double* ux, double* uy, double* p, double* totals,
                        hipStream_t stream);
 

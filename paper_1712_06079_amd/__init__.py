@@ -32,7 +32,7 @@ class _CParams(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("eos", C.c_int32), ("force", C.c_int32),
                 ("grad", C.c_int32), ("prec", C.c_int32), ("tau", C.c_double), ("a", C.c_double),
                 ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double), ("T", C.c_double),
-                ("k", C.c_double), ("g", C.c_double), ("A", C.c_double)]
+                ("k", C.c_double), ("g", C.c_double), ("A", C.c_double), ("walls", C.c_int32), ("reserved", C.c_int32)]
 
 
 @dataclass
@@ -53,10 +53,11 @@ class Params:
     k: float = 0.01
     g: float = 1.0
     A: float = 0.0
+    walls: int = 0
 
     def c(self) -> _CParams:
         return _CParams(self.nx, self.ny, EOS[self.eos], FORCE[self.force], GRAD[self.grad], PREC[self.prec],
-                        self.tau, self.a, self.b, self.R, self.omega, self.T, self.k, self.g, self.A)
+                        self.tau, self.a, self.b, self.R, self.omega, self.T, self.k, self.g, self.A, int(self.walls), 0)
 
 
 _lib = None

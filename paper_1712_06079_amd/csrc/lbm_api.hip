@@ -61,6 +61,8 @@ lbm_status validate(const lbm_params* p) {
     if (!(p->k > 0) || !std::isfinite(p->k)) return fail(LBM_EINVAL, "k = %g must be > 0", p->k);
     if (!std::isfinite(p->g) || !std::isfinite(p->A) || !std::isfinite(p->omega))
         return fail(LBM_EINVAL, "non-finite g, A or omega");
+    if (p->walls < 0 || p->walls > 1 || p->reserved != 0) return fail(LBM_EINVAL, "walls must be 0 or 1, reserved 0");
+    if (p->walls && p->grad == LBM_GRAD_CDM9) return fail(LBM_EUNSUPPORTED, "walls with the Eq. 15 gradient");
     return LBM_OK;
 }
 
@@ -119,7 +121,7 @@ int march_rows(const lbm_domain* d) { return d->tile_y ? d->tile_y : 8; }
 // The marching kernel needs the geometric form along y (HDM, ny > 2R + 1) and
 // a y period longer than its look-ahead.
 bool march_eligible(const lbm_domain* d) {
-    if (d->p.grad != LBM_GRAD_HDM) return false;
+    if (d->p.grad != LBM_GRAD_HDM || d->p.walls) return false;
     return d->p.prec == LBM_F32 ? lbm::march_fits<float>(d->p.ny, march_rows(d))
                                 : lbm::march_fits<double>(d->p.ny, march_rows(d));
 }
@@ -172,7 +174,8 @@ int auto_tile(const lbm_domain* d) {
 
 lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f_out, void* phi_out, hipStream_t s) {
     if (d->variant == 3 && !march_eligible(d))
-        return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient and a longer y axis (ny = %d)", d->p.ny);
+        return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient, a periodic and longer y axis (ny = %d)", d->p.ny);
+    if (d->variant == 1 && d->p.walls) return fail(LBM_EUNSUPPORTED, "the two-pass reference kernel has no walls");
     lbm_status st = LBM_OK;
     dispatch(d, [&](auto real, auto force) {
         using Real = decltype(real);
@@ -342,10 +345,12 @@ lbm_status lbm_init(const lbm_params* p, void* workspace, size_t workspace_bytes
         lbm_host::cdm_row(1, d->dx);
         lbm_host::cdm_row(1, d->dy);
     } else {
+        // between walls the y lines continue by reflection: the periodic row of 2 ny points
+        const int nyl = p->walls ? 2 * p->ny : p->ny;
         d->tx = lbm_host::hdm_taps(p->nx, radius);
-        d->ty = lbm_host::hdm_taps(p->ny, radius);
+        d->ty = lbm_host::hdm_taps(nyl, radius);
         lbm_host::hdm_row(p->nx, d->tx, d->dx);
-        lbm_host::hdm_row(p->ny, d->ty, d->dy);
+        lbm_host::hdm_row(nyl, d->ty, d->dy);
     }
     d->off_tab = d->off_scr + L.scr;
     build_tables(d);
@@ -614,6 +619,7 @@ lbm_status adjoint_check(lbm_domain* d, const void* adj_ws, size_t adj_ws_bytes)
     if (d->p.prec != LBM_F64) return fail(LBM_EUNSUPPORTED, "the adjoint step is implemented for FP64 domains");
     if (d->p.force == LBM_FORCE_HYBRID) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the SC and ZC forces");
     if (d->p.grad == LBM_GRAD_CDM9) return fail(LBM_EUNSUPPORTED, "the adjoint step supports the Eq. 20 and Eq. 14 gradients");
+    if (d->p.walls) return fail(LBM_EUNSUPPORTED, "the adjoint step is periodic only");
     if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
     AdjLayout L = adj_layout(d);
     if (adj_ws_bytes < L.total) return fail(LBM_ENOMEM, "adjoint workspace %zu < %zu bytes", adj_ws_bytes, L.total);

@@ -193,7 +193,21 @@ struct StepArgs {
     // 1: the gradient is the weighted D2Q9 difference of Eq. 15 (with the
     // 1/c_s^2 factor) instead of a per-axis stencil.
     int grad9;
+    // 1: no-slip walls at y = -1/2 and ny - 1/2 (rows continue past a wall
+    // by reflection; populations crossing it bounce back).
+    int walls;
 };
+
+// Lattice row of row index y (any integer): periodic, or between walls at
+// -1/2 and n - 1/2, where the rows continue by reflection (period 2n).
+__device__ inline int ymap(int y, int n, int walls) {
+    if (!walls) return wrap(y, n);
+    const int t = wrap(y, 2 * n);
+    return t < n ? t : 2 * n - 1 - t;
+}
+
+// Opposite D2Q9 direction (order 0, +x, +y, -x, -y, ++, -+, --, +-).
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i < 5 ? 1 + (i + 1) % 4 : 5 + (i - 3) % 4); }
 
 // Eq. 15 with the factor 1/c_s^2 = 3 at the centre of a 3 x 3 neighbourhood
 // (m: row y-1, c: row y, p: row y+1; index 0, 1, 2 = x-1, x, x+1):

@@ -165,18 +165,18 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
         stage_issue(scol, tid, [&](int i) {
             const int j = min(i, B9 - 1);  // past the block: a duplicate, not read
             const int r = j / B9W, c = j - r * B9W;
-            const int yw = wrap(y0 - 2 + r, ny), xw = wrap(x0 - 2 + c, nx);
+            const int yw = ymap(y0 - 2 + r, ny, a.walls), xw = wrap(x0 - 2 + c, nx);
             return (double)phin[(long)yw * pitch + xw];
         });
     } else {
         stage_issue(srow, tid, [&](int i) {
             const int r = i / S::RW, c = i - r * S::RW;
-            const int yw = wrap(y0 - 1 + r, ny), xw = wrap(x0 - 1 - RX + c, nx);
+            const int yw = ymap(y0 - 1 + r, ny, a.walls), xw = wrap(x0 - 1 - RX + c, nx);
             return (double)phin[(long)yw * pitch + xw];
         });
         stage_issue(scol, tid, [&](int i) {
             const int r = i / CW, c = i - r * CW;
-            const int yw = wrap(y0 - 1 - RY + r, ny), xw = wrap(x0 - 1 + c, nx);
+            const int yw = ymap(y0 - 1 - RY + r, ny, a.walls), xw = wrap(x0 - 1 + c, nx);
             return (double)phin[(long)yw * pitch + xw];
         });
     }
@@ -191,7 +191,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     for (int i = 0; i < S::NC; ++i) {
         const int c = min(tid + i * NT, S::NCELL - 1);  // past the end: a duplicate, never used
         const int cy = c / CW, cx = c - cy * CW;
-        const int xw = wrap(x0 - 1 + cx, nx), yw = wrap(y0 - 1 + cy, ny);
+        const int xw = wrap(x0 - 1 + cx, nx), yw = ymap(y0 - 1 + cy, ny, a.walls);
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[i][q] = a.f_in[fidx(xw, yw, q, nxb)];
     }
@@ -304,7 +304,9 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     }
     __syncthreads();
 
-    // Phase 4: pull streaming, aligned stores, epilogue phi_{t+1}.
+    // Phase 4: pull streaming, aligned stores, epilogue phi_{t+1}.  Between
+    // walls a population that would enter row 0 from below (or row ny-1 from
+    // above) is the one that left the same site towards the wall, reversed.
 #pragma unroll
     for (int i = 0; i < S::NI; ++i) {
         const int c = tid + i * NT;
@@ -313,9 +315,12 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
             const int x = x0 + lx, y = y0 + ly;
             if (x < nx && y < ny) {
                 double g[Q];
+                const bool low = a.walls && y == 0, high = a.walls && y == ny - 1;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const Real v = fst[q * S::NCELL + (ly + 1 - ey(q)) * CW + (lx + 1 - ex(q))];
+                    const bool back = (low && ey(q) > 0) || (high && ey(q) < 0);
+                    const Real v = back ? fst[opp(q) * S::NCELL + (ly + 1) * CW + (lx + 1)]
+                                        : fst[q * S::NCELL + (ly + 1 - ey(q)) * CW + (lx + 1 - ex(q))];
                     a.f_out[fidx(x, y, q, nxb)] = v;
                     g[q] = (double)v;
                 }

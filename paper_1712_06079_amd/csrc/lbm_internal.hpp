@@ -86,13 +86,15 @@ lbm::StepArgs<Real> make_args(const lbm_domain* d, int in_buf, int out_buf) {
     // geometric recursion along axes longer than 2R + 1 (HDM only)
     const int R = lbm::Radius<Real>::value;
     a.rec_x = (d->p.grad == LBM_GRAD_HDM && d->p.nx > 2 * R + 1) ? 1 : 0;
-    a.rec_y = (d->p.grad == LBM_GRAD_HDM && d->p.ny > 2 * R + 1) ? 1 : 0;
+    // (between walls the y lines continue by reflection: period 2 ny)
+    a.rec_y = (d->p.grad == LBM_GRAD_HDM && (d->p.walls ? 2 * d->p.ny : d->p.ny) > 2 * R + 1) ? 1 : 0;
     double C = 0.0;
     lbm_host::hdm_infinite(&a.rr, &a.rd1, &a.rd2, &C);
     a.rr3 = a.rr * a.rr * a.rr;
     a.rr4 = a.rr3 * a.rr;
     a.rK = C / (1.0 - a.rr);
     a.grad9 = d->p.grad == LBM_GRAD_CDM9 ? 1 : 0;
+    a.walls = d->p.walls ? 1 : 0;
     return a;
 }
 

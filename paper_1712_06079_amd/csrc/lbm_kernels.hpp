@@ -137,7 +137,7 @@ __device__ inline void stage_lds(double* __restrict__ dst, Src src) {
 
 template <typename Real, int TY, typename P>
 __device__ inline void stage_cross(Cross<Real, TY>& s, const P* __restrict__ phi, int x0, int y0, int nx,
-                                   int ny, int pitch) {
+                                   int ny, int pitch, int walls = 0) {
     using C = Cross<Real, TY>;
     stage_lds<TY * C::RW, 8>(&s.row[0][0], [&](int i) {
         const int r = i / C::RW, c = i - r * C::RW;
@@ -147,7 +147,7 @@ __device__ inline void stage_cross(Cross<Real, TY>& s, const P* __restrict__ phi
     });
     stage_lds<C::CH * BX, 8>(&s.col[0][0], [&](int i) {
         const int r = i / BX, c = i - r * BX;
-        const int y = wrap(y0 - C::J + r, ny);
+        const int y = ymap(y0 - C::J + r, ny, walls);
         const int x = min(x0 + c, nx - 1);
         return (double)phi[(long)y * pitch + x];
     });
@@ -277,9 +277,13 @@ __device__ inline double wave_sum(double v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+// max that keeps a NaN (fmax would drop it and report the largest finite
+// speed of a field that has gone non-finite)
+__device__ inline double nanmax(double a, double b) { return (a != a || b != b) ? a + b : fmax(a, b); }
+
 __device__ inline double wave_max(double v) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o >= 1; o >>= 1) v = nanmax(v, __shfl_xor(v, o, 64));
     return v;
 }
 
@@ -293,7 +297,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const auto* phin = static_cast<const typename PhiStore<Real, FORCE>::type*>(a.phi_in);
-    stage_cross<Real, TY>(s, phin, x0, y0, a.nx, a.ny, pitch);
+    stage_cross<Real, TY>(s, phin, x0, y0, a.nx, a.ny, pitch, a.walls);
     if (a.grad9) stage_block9<TY>(b9, phin, x0, y0, a.nx, a.ny, pitch);
     __syncthreads();
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
@@ -320,7 +324,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
         m += dr;
         px += dr * vx;
         py += dr * vy;
-        vmax = fmax(vmax, sqrt(vx * vx + vy * vy));
+        vmax = nanmax(vmax, sqrt(vx * vx + vy * vy));
     }
     m = wave_sum(m);
     px = wave_sum(px);
@@ -334,7 +338,7 @@ __global__ void __launch_bounds__(NT) k_moments(StepArgs<Real> a, double* __rest
     if (threadIdx.x == 0) {
         double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
         for (int k = 0; k < NT / BX; ++k) {
-            t0 += red[0][k]; t1 += red[1][k]; t2 += red[2][k]; t3 = fmax(t3, red[3][k]);
+            t0 += red[0][k]; t1 += red[1][k]; t2 += red[2][k]; t3 = nanmax(t3, red[3][k]);
         }
         long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
         partial[4 * b + 0] = t0;
@@ -351,7 +355,7 @@ static __global__ void __launch_bounds__(NT) __attribute__((unused)) k_totals(co
     double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     for (long b = threadIdx.x; b < nblocks; b += NT) {
         t0 += partial[4 * b + 0]; t1 += partial[4 * b + 1]; t2 += partial[4 * b + 2];
-        t3 = fmax(t3, partial[4 * b + 3]);
+        t3 = nanmax(t3, partial[4 * b + 3]);
     }
     t0 = wave_sum(t0); t1 = wave_sum(t1); t2 = wave_sum(t2); t3 = wave_max(t3);
     const int w = threadIdx.x / BX;
@@ -359,7 +363,7 @@ static __global__ void __launch_bounds__(NT) __attribute__((unused)) k_totals(co
     __syncthreads();
     if (threadIdx.x == 0) {
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int k = 0; k < NT / BX; ++k) { s0 += red[0][k]; s1 += red[1][k]; s2 += red[2][k]; s3 = fmax(s3, red[3][k]); }
+        for (int k = 0; k < NT / BX; ++k) { s0 += red[0][k]; s1 += red[1][k]; s2 += red[2][k]; s3 = nanmax(s3, red[3][k]); }
         out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3;
     }
 }

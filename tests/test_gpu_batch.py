@@ -44,7 +44,7 @@ def sweep_params(n, seed, prec="f64", shapes=None):
 
 def to_oracle(p):
     return O.Params(nx=p.nx, ny=p.ny, eos=p.eos, force=p.force, grad=p.grad, tau=p.tau, a=p.a, b=p.b, R=p.R,
-                    omega=p.omega, T=p.T, k=p.k, g=p.g, A=p.A)
+                    omega=p.omega, T=p.T, k=p.k, g=p.g, A=p.A, walls=p.walls)
 
 
 SHAPES = ([128, 70, 256, 64, 512, 130, 200, 96], [8, 9, 32, 16, 8, 33, 17, 8])
@@ -147,6 +147,25 @@ def test_cdm9_batch(force):
     for i in (1, 6):
         po = to_oracle(ps[i])
         ref = O.moments(po, O.run(po, O.init(po, rhos[i]), 25))["rho"]
+        got = b.domain(i).moments()["rho"].cpu().numpy()
+        assert np.max(np.abs(got - ref) / ref) < 1e-12, i
+
+
+def test_batch_with_walls():
+    """Channels and periodic domains in one batch (the walls are a per-domain
+    setting): bitwise the single-domain kernel, and the oracle within 1e-12."""
+    ps, rhos = sweep_params(8, 23, "f64", SHAPES)
+    for i, p in enumerate(ps):
+        p.walls = i % 2
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    b.step(30)
+    for i, (p, r) in enumerate(zip(ps, rhos)):
+        d = L.Domain(p, dev(r))
+        d.step(30)
+        assert np.array_equal(b.domain(i).populations().cpu().numpy(), d.populations().cpu().numpy()), i
+    for i in (1, 5):
+        po = to_oracle(ps[i])
+        ref = O.moments(po, O.run(po, O.init(po, rhos[i]), 30))["rho"]
         got = b.domain(i).moments()["rho"].cpu().numpy()
         assert np.max(np.abs(got - ref) / ref) < 1e-12, i
 

@@ -25,7 +25,7 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 
 def lib_params(po: O.Params, prec="f64") -> L.Params:
     return L.Params(nx=po.nx, ny=po.ny, eos=po.eos, force=po.force, grad=po.grad, prec=prec, tau=po.tau, a=po.a,
-                    b=po.b, R=po.R, omega=po.omega, T=po.T, k=po.k, g=po.g, A=po.A)
+                    b=po.b, R=po.R, omega=po.omega, T=po.T, k=po.k, g=po.g, A=po.A, walls=po.walls)
 
 
 def dev(a):
@@ -412,3 +412,80 @@ def test_sigma_from_gpu_slab():
     kappa = 0.01
     s_gpu, _ = L.sigma_slab(kappa, got)
     assert abs(s_gpu / O.sigma_slab(kappa, ref) - 1) < 1e-11
+
+
+def wall_case(eos, force, nx, ny, seed):
+    """A droplet resting near the lower wall of a channel (walls at y = -1/2 and
+    ny - 1/2), with velocity noise."""
+    po = PINS.eos_params(eos)
+    po.nx, po.ny, po.force, po.walls = nx, ny, force, 1
+    po.A = 0.3 if force == "hybrid" else 0.0
+    tc, _ = O.critical(po)
+    po.T = 0.8 * tc
+    rv, rl, _ = O.maxwell(po, po.T)
+    r = min(nx, ny) / 4.0
+    rho0 = I.droplet(nx, ny, rv, rl, r, 4.0, cx=nx * 0.45, cy=r + 2.0, noise=1e-3 * rv, seed=seed)
+    ux0 = I.uniform_noise((ny, nx), 1e-3, seed + 1)
+    uy0 = I.uniform_noise((ny, nx), 1e-3, seed + 2)
+    return po, rho0, ux0, uy0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])
+@pytest.mark.parametrize("nx,ny", [(70, 37), (96, 150)])
+def test_walls_match_oracle(nx, ny, force, prec):
+    """No-slip walls (halfway bounce-back, mirror closure of Eq. 20) on the tile
+    kernel: a short channel (the y row is the whole periodic row of the 2 ny
+    reflected line) and a tall one (its geometric form), every force, 60 steps."""
+    po, rho0, ux0, uy0 = wall_case("vdw", force, nx, ny, seed=nx + ny)
+    ref = oracle_run(po, rho0, 60, ux0, uy0)
+    got = gpu_run(po, rho0, 60, prec, ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
+    assert abs(got["totals"][0] / ref["rho"].sum() - 1) < TOL[prec]
+
+
+@pytest.mark.parametrize("tile", [4, 8, 16])
+def test_walls_tile_heights(tile):
+    po, rho0, ux0, uy0 = wall_case("pr", "zc", 130, 45, seed=3)
+    po.grad = "hdm"
+    ref = oracle_run(po, rho0, 30, ux0, uy0)
+    got = gpu_run(po, rho0, 30, "f64", ux0, uy0, variant=2, tile=tile)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+    assert np.max(np.abs(got["f"] - ref["f"])) < 1e-12 * np.max(np.abs(ref["f"]))
+
+
+def test_walls_cdm_and_moments():
+    """Eq. 14 with the mirror closure, and the output moments next to the walls
+    (the half-step velocity needs the wall-closed force), element by element."""
+    po, rho0, ux0, uy0 = wall_case("cs", "sc", 64, 40, seed=5)
+    po.grad = "cdm"
+    ref = oracle_run(po, rho0, 40, ux0, uy0)
+    got = gpu_run(po, rho0, 40, "f64", ux0, uy0)
+    assert rel_err(got["rho"], ref["rho"]) < 1e-12
+    rho = ref["rho"]
+    for c in ("x", "y"):
+        bound = 4e-12 * (rho + np.abs(ref["F" + c])) / rho
+        assert np.max(np.abs(got["v" + c] - ref["v" + c]) / bound) < 1.0
+
+
+def test_walls_unsupported_paths():
+    po, rho0, _, _ = wall_case("vdw", "sc", 64, 100, seed=7)
+    d = L.Domain(lib_params(po), dev(rho0))
+    for variant in (1, 3):
+        d.set_kernel(variant, 8)
+        with pytest.raises(L.LBMError) as e:
+            d.step(1)
+        assert e.value.status == 5
+    d.set_kernel(0, 0)
+    st = d.new_states(1)
+    d.save_state(st[0])
+    lam = torch.zeros((9, 100, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LBMError) as e:
+        d.adjoint_step(st[0], lam, torch.empty_like(lam), torch.zeros(2, dtype=torch.float64, device="cuda"),
+                       d.adjoint_workspace())
+    assert e.value.status == 5
+    p = lib_params(po)
+    p.grad = "cdm9"
+    with pytest.raises(L.LBMError) as e:
+        L.Domain(p, dev(rho0))
+    assert e.value.status == 5
