@@ -84,12 +84,18 @@ def _make_workload(name: str, seed: int):
     raise ValueError(name)
 
 
-def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0, chunks: int = 0):
+def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, tile: int = 0, chunks: int = 0,
+            device_warmup_s: float = 0.0):
     """Time exactly `steps` steps after `warmup` untimed ones with one pair of
     HIP events around the timed launches, recorded on the stream the library
     launches on (torch's current stream).  The mean launch duration is that
     span over `steps`: the launches are back to back, so it is the kernel's
-    average duration plus the (sub-microsecond) gaps between launches."""
+    average duration plus the (sub-microsecond) gaps between launches.
+
+    With `device_warmup_s` > 0 a second domain built from the same inputs
+    runs the same kernel for that long first and is then freed (see
+    `device_warmup`); the timed domain itself still gets exactly `warmup`
+    untimed steps."""
     import torch
 
     import paper_1712_06079_amd as L
@@ -101,6 +107,13 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     d.set_kernel(variant, tile)
     d.set_chunks(chunks)
     stream = torch.cuda.current_stream()
+    warm = 0.0
+    if device_warmup_s > 0:
+        scratch = L.Domain(p, t(rho0), t(ux0), t(uy0))
+        scratch.set_kernel(variant, tile)
+        scratch.set_chunks(chunks)
+        warm = device_warmup(scratch, device_warmup_s, stream)
+        del scratch
     d.step(warmup, stream=stream)
     total0 = torch.cuda.Event(enable_timing=True)
     total1 = torch.cuda.Event(enable_timing=True)
@@ -122,7 +135,7 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     return {
         "desc": desc, "params": p, "mlups": mlups, "ms_per_step": ms_total / steps, "wall_s": wall,
         "launch_ms_mean": launch_ms, "achieved_gbs": achieved, "alg_bytes_per_launch": alg_bytes, "finite": ok,
-        "domain": d,
+        "domain": d, "device_warmup_s": round(warm, 2),
     }
 
 
@@ -822,6 +835,27 @@ def size_curve(sizes, steps: int):
     return out
 
 
+def device_warmup(dom, seconds: float, stream) -> float:
+    """Step `dom` (a throw-away domain) in groups of 50 launches for `seconds`
+    of wall time; returns the time spent.
+
+    From idle, and also right after a different kernel, launches 5-25 of a
+    fresh 4096^2 step run 10-20 % slower than in steady state (per-launch HIP
+    events: 0.58-0.67 ms against 0.53 ms for FP64, 0.41-0.45 ms against
+    0.35 ms for FP32) and the rate settles after about 50 launches: the
+    device's clock and power management adapting to the load, not the
+    kernel.  A short timed window right after a few warm-up steps measures
+    that transient; holding the device under the same kernel first takes it
+    out."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        dom.step(50, stream=stream)
+        torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -926,6 +960,8 @@ def main():
     ap.add_argument("--no-other-prec", action="store_true", help="skip the second-precision run")
     ap.add_argument("--copy-probe", action="store_true", help="only run the streaming-copy calibration kernel")
     ap.add_argument("--no-probe", dest="probe", action="store_false", help="skip the streaming probes")
+    ap.add_argument("--device-warmup", type=float, default=2.0,
+                    help="seconds of the same kernel on a throw-away domain before the timed domain's warm-up (0 = none)")
     ap.add_argument("--steady-steps", type=int, default=2000,
                     help="steps timed right after the headline window on the same domain (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
@@ -948,16 +984,16 @@ def main():
         print("bench.py: launched with WORLD_SIZE > 1; the library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
-    # The streaming probe runs first: besides the attainable rates it reports,
-    # its second of memory traffic takes the device out of the power state it
-    # idles in.  From idle, launches 5-25 of the step run 10-20 % slower than
-    # in steady state (a transient of the device, not of the kernel), which a
-    # short timed window right after a few warm-up steps would measure.
+    # Before the domain's own warm-up steps the device is held under the same
+    # kernel on a throw-away domain for `--device-warmup` seconds (see
+    # device_warmup): the timed domain still gets exactly `--warmup` untimed
+    # steps and `--steps` timed ones.
     probe = stream_probe() if args.probe else None
     if probe:
         print(f"[bench] streaming probe: copy {probe['copy']['GBps']:.0f}, read {probe['read']['GBps']:.0f}, "
               f"write {probe['write']['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
-    r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile, args.chunks)
+    r = run_gpu(args.workload, args.prec, args.steps, args.warmup, args.variant, args.tile, args.chunks,
+                args.device_warmup)
     print(f"[bench] {args.workload} {args.prec}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
           f"{r['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
     steady = steady_state(r, args.steady_steps) if args.steady_steps > 0 else None
@@ -969,7 +1005,8 @@ def main():
     other = None
     if not args.no_other_prec:
         op = "f32" if args.prec == "f64" else "f64"
-        o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile, args.chunks)
+        o = run_gpu(args.workload, op, args.steps, args.warmup, args.variant, args.tile, args.chunks,
+                    args.device_warmup)
         print(f"[bench] {args.workload} {op}: {o['mlups']:.0f} MLUPS, {o['ms_per_step']:.4f} ms/step, "
               f"{o['achieved_gbs']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
         osteady = steady_state(o, args.steady_steps) if args.steady_steps > 0 else None
@@ -1016,6 +1053,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    line["device_warmup_s"] = r["device_warmup_s"]
     if steady:
         line["steady_state"] = steady
     if other:
