@@ -59,7 +59,7 @@ typedef enum { LBM_GRAD_HDM = 0, LBM_GRAD_CDM = 1, LBM_GRAD_CDM9 = 2 } lbm_grad;
 typedef enum { LBM_F64 = 0, LBM_F32 = 1 } lbm_prec;
 
 /* Problem statement of one periodic domain (Secs. 2, 4, 5.2).
- *  nx, ny  lattice size, each >= 5
+ *  nx, ny  lattice size, each in [5, 2^21], nx * ny <= 2^31
  *  eos     equation of state: VDW (Eq. 24), PR (Eq. 28), CS (Eq. 29 read with
  *          the Carnahan-Starling denominator (1 - b rho/4)^3), RK (Eq. 27,
  *          alpha = 1/sqrt(T)), RKS (Eq. 27 with the Soave alpha(T_r))

@@ -50,7 +50,8 @@ lbm_host::EosConst eos_const(const lbm_params* p) {
 lbm_status validate(const lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
     if (p->nx < 5 || p->ny < 5) return fail(LBM_EINVAL, "lattice %d x %d: each side must be >= 5", p->nx, p->ny);
-    if ((long)p->nx * p->ny > (1L << 31)) return fail(LBM_EINVAL, "lattice too large");
+    if (p->nx > (1 << 21) || p->ny > (1 << 21) || (long)p->nx * p->ny > (1L << 31))
+        return fail(LBM_EINVAL, "lattice %d x %d: each side must be <= 2^21 and nx * ny <= 2^31", p->nx, p->ny);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau = %g must be > 1/2", p->tau);
     if (p->eos < 0 || p->eos > 4) return fail(LBM_EINVAL, "unknown eos %d", p->eos);
     if (p->force < 0 || p->force > 2) return fail(LBM_EINVAL, "unknown force %d", p->force);

@@ -151,6 +151,22 @@ __device__ inline int wrap(int v, int n) {
     return v;
 }
 
+// v mod n for |v| < 2^23 and 0 < n <= 2^22 (lattice sides are at most 2^21),
+// without a loop or a branch: v converts to FP32 exactly, the quotient estimate
+// floor(v / n) from the FP32 reciprocal is exact or off by one (relative error
+// of rcp and product below 2^-21 on a quotient below 2^22 in size), and one
+// correction each way brings the remainder into [0, n).  Kernels that wrap many
+// staged indices per tile use it instead of wrap(), whose correction loops
+// compile to divergent branches.
+__device__ inline int wrap_fast(int v, int n) {
+    const float rn = __builtin_amdgcn_rcpf((float)n);
+    const int q = (int)floorf((float)v * rn);
+    int r = v - __mul24(q, n);
+    r += r < 0 ? n : 0;
+    r -= r >= n ? n : 0;
+    return r;
+}
+
 // Coefficient tables of a domain's Eq. 20 stencil, in device memory (a small
 // region of the domain workspace); kernels read them with uniform (scalar)
 // loads.  Keeping them out of the kernel arguments keeps launches cheap.
@@ -204,6 +220,13 @@ __device__ inline int ymap(int y, int n, int walls) {
     if (!walls) return wrap(y, n);
     const int t = wrap(y, 2 * n);
     return t < n ? t : 2 * n - 1 - t;
+}
+
+// ymap through wrap_fast (the same result for |y| < 2^22, n <= 2^21).
+__device__ inline int ymap_fast(int y, int n, int walls) {
+    const int per = walls ? 2 * n : n;
+    const int t = wrap_fast(y, per);
+    return t >= n ? per - 1 - t : t;
 }
 
 // Opposite D2Q9 direction (order 0, +x, +y, -x, -y, ++, -+, --, +-).

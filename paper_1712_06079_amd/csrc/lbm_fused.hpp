@@ -161,23 +161,20 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     // also wait for the populations).
     StageRegs<CH * S::RW> srow;
     StageRegs<S::VH * CW> scol;
+    // (plane offsets fit in 24-bit products: a plane has fewer than 2^31
+    // elements and its rows fewer than 2^22)
+    auto phi_at = [&](int yw, int xw) { return (double)phin[(unsigned)(__mul24(yw, pitch) + xw)]; };
     if constexpr (G9) {
-        stage_issue(scol, tid, [&](int i) {
-            const int j = min(i, B9 - 1);  // past the block: a duplicate, not read
-            const int r = j / B9W, c = j - r * B9W;
-            const int yw = ymap(y0 - 2 + r, ny, a.walls), xw = wrap(x0 - 2 + c, nx);
-            return (double)phin[(long)yw * pitch + xw];
+        // past the block: rows beyond it repeat its last row, not read
+        stage_issue_rc<S::VH * CW, B9W>(scol, tid, [&](int r, int c) {
+            return phi_at(ymap_fast(y0 - 2 + min(r, CH + 1), ny, a.walls), wrap_fast(x0 - 2 + c, nx));
         });
     } else {
-        stage_issue(srow, tid, [&](int i) {
-            const int r = i / S::RW, c = i - r * S::RW;
-            const int yw = ymap(y0 - 1 + r, ny, a.walls), xw = wrap(x0 - 1 - RX + c, nx);
-            return (double)phin[(long)yw * pitch + xw];
+        stage_issue_rc<CH * S::RW, S::RW>(srow, tid, [&](int r, int c) {
+            return phi_at(ymap_fast(y0 - 1 + r, ny, a.walls), wrap_fast(x0 - 1 - RX + c, nx));
         });
-        stage_issue(scol, tid, [&](int i) {
-            const int r = i / CW, c = i - r * CW;
-            const int yw = ymap(y0 - 1 - RY + r, ny, a.walls), xw = wrap(x0 - 1 + c, nx);
-            return (double)phin[(long)yw * pitch + xw];
+        stage_issue_rc<S::VH * CW, CW>(scol, tid, [&](int r, int c) {
+            return phi_at(ymap_fast(y0 - 1 - RY + r, ny, a.walls), wrap_fast(x0 - 1 + c, nx));
         });
     }
 
@@ -191,7 +188,7 @@ __device__ inline void fused_tile(const StepArgs<Real>& a, int x0, int y0, doubl
     for (int i = 0; i < S::NC; ++i) {
         const int c = min(tid + i * NT, S::NCELL - 1);  // past the end: a duplicate, never used
         const int cy = c / CW, cx = c - cy * CW;
-        const int xw = wrap(x0 - 1 + cx, nx), yw = ymap(y0 - 1 + cy, ny, a.walls);
+        const int xw = wrap_fast(x0 - 1 + cx, nx), yw = ymap_fast(y0 - 1 + cy, ny, a.walls);
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[i][q] = a.f_in[fidx(xw, yw, q, nxb)];
     }

@@ -106,6 +106,28 @@ __device__ inline void stage_issue(StageRegs<N>& s, int tid, Src src) {
     }
 }
 
+// stage_issue over an array of rows of W elements: src(r, c) receives the
+// row and column of element i = tid + j NT, advanced from one division per
+// call (the per-element quotient would take a high multiply per load).
+template <int N, int W, typename Src>
+__device__ inline void stage_issue_rc(StageRegs<N>& s, int tid, Src src) {
+    constexpr int LR = (N - 1) / W, LC = (N - 1) - LR * W;  // the last element
+    constexpr int DR = NT / W, DC = NT - DR * W;             // one step of NT
+    int r = tid / W, c = tid - r * W;
+#pragma unroll
+    for (int j = 0; j < StageRegs<N>::PER; ++j) {
+        // past the end: reload the last element (not stored)
+        const bool in = tid + j * NT < N;
+        s.v[j] = src(in ? r : LR, in ? c : LC);
+        r += DR;
+        c += DC;
+        if (c >= W) {
+            c -= W;
+            ++r;
+        }
+    }
+}
+
 template <int N>
 __device__ inline void stage_commit(double* __restrict__ dst, int tid, const StageRegs<N>& s) {
 #pragma unroll
