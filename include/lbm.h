@@ -329,19 +329,29 @@ lbm_status lbm_batch_step_separate(lbm_batch* b, int64_t nsteps, hipStream_t str
 lbm_domain* lbm_batch_domain(lbm_batch* b, int32_t i);
 
 /* Scheduler setting: tile_y rows per tile (4 or 8), order (0 = domain order,
- * 1 = largest domains first, 2 = round robin over domains), grid = workgroups
- * of the persistent launch (0 = one per tile).  set copies the new worklist on
+ * 1 = largest domains first, 2 = round robin over domains, 3 = each domain's
+ * tiles on the workgroups of one XCD: worklist position p goes to workgroup
+ * p mod grid, which the hardware places on XCD (p mod grid) mod 8), grid =
+ * workgroups of the persistent launch (0 = one per tile).  set copies the new worklist on
  * `stream` and synchronises it: batched steps queued on `stream` before the
  * call finish with the old schedule.  Steps queued on other streams must be
  * complete (the caller synchronises them).  LBM_EINVAL for other values. */
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid, hipStream_t stream);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* order, int32_t* grid);
 
-/* Time every scheduler candidate over probe_steps batched steps with HIP
- * events, keep the fastest, and restore every domain's state as it was on
- * entry (synchronises `stream`).  report (nullable) receives a JSON object of
- * the per-step times in ms and the choice. */
+/* Time every scheduler candidate (tile_y 4 and 8, the four orders, grid 0,
+ * 256, 512, 1024, 2048) over probe_steps batched steps with HIP events, keep
+ * the fastest, and restore every domain's state as it was on entry
+ * (synchronises `stream`).  report (nullable) receives a JSON object of the
+ * per-step times in ms, "cached": false and the choice.  The choice is kept
+ * for the rest of the process under a key of the device architecture, the
+ * batch's precision, force, gradient and domain shapes in order; a later call
+ * for a batch with the same key applies it without timing (report
+ * {"cached": true, "best": ...}). */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t stream, char* report, size_t report_len);
+
+/* Forget every autotuner choice kept by this process (thread-safe). */
+void lbm_batch_tune_cache_clear(void);
 
 /* Per-domain non-finite check (synchronises): flags[i] = 1 if domain i holds a
  * non-finite density (host array of n int32); returns LBM_ENONFINITE if any. */

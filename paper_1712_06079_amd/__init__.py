@@ -375,6 +375,8 @@ class Batch:
         L.lbm_batch_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
         L.lbm_batch_destroy.argtypes = [_VP]
         L.lbm_batch_destroy.restype = None
+        L.lbm_batch_tune_cache_clear.argtypes = []
+        L.lbm_batch_tune_cache_clear.restype = None
         for fn in ("lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_separate",
                    "lbm_batch_set_schedule", "lbm_batch_get_schedule", "lbm_batch_autotune", "lbm_batch_check_finite"):
             getattr(L, fn).restype = C.c_int
@@ -430,6 +432,11 @@ class Batch:
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
         check(self._sigs().lbm_batch_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"tile_y": a.value, "order": b.value, "grid": c.value}
+
+    @classmethod
+    def tune_cache_clear(cls):
+        """Forget the autotuner choices kept by this process."""
+        cls._sigs().lbm_batch_tune_cache_clear()
 
     def autotune(self, probe_steps: int = 20, stream=None) -> dict:
         import json

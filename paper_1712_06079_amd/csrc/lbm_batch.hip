@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -48,8 +50,13 @@ constexpr int GRAPH_STEPS = 16;  // launches per captured graph (even: parity is
 
 size_t desc_size(int prec) { return prec == LBM_F32 ? sizeof(lbm::StepArgs<float>) : sizeof(lbm::StepArgs<double>); }
 
-// Worklist of (domain, x0, y0) tiles in the requested order.
-std::vector<lbm::BatchTile> make_tiles(const lbm_batch* b, int ty, int order) {
+// Worklist of (domain, x0, y0) tiles in the requested order.  Worklist
+// position p is taken by workgroup p mod G of a grid of G workgroups, and
+// workgroup w runs on XCD w mod 8: order 3 places each domain's tiles at
+// positions of one XCD (domains largest first, each to the XCD with the most
+// free positions; what does not fit fills the remaining positions), so the
+// potential halos that neighbouring tiles share are read into one L2.
+std::vector<lbm::BatchTile> make_tiles(const lbm_batch* b, int ty, int order, int grid) {
     std::vector<std::vector<lbm::BatchTile>> per(b->n);
     for (int d = 0; d < b->n; ++d) {
         const lbm_params& p = b->doms[d]->p;
@@ -58,10 +65,37 @@ std::vector<lbm::BatchTile> make_tiles(const lbm_batch* b, int ty, int order) {
     }
     std::vector<int> idx(b->n);
     for (int d = 0; d < b->n; ++d) idx[d] = d;
-    if (order == 1)  // largest domains first (longest-processing-time order)
+    if (order == 1 || order == 3)  // largest domains first (longest-processing-time order)
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return per[a].size() > per[c].size(); });
     std::vector<lbm::BatchTile> out;
-    if (order == 2) {  // round robin: one tile of each domain in turn
+    if (order == 3) {
+        size_t total = 0;
+        for (const auto& v : per) total += v.size();
+        const size_t G = grid > 0 ? std::min<size_t>((size_t)grid, total) : total;
+        std::vector<std::vector<size_t>> pos(lbm::NXCD);
+        for (size_t p = 0; p < total; ++p) pos[(p % G) % lbm::NXCD].push_back(p);
+        out.assign(total, lbm::BatchTile{0, 0, 0, 0});
+        std::vector<char> used(total, 0);
+        std::vector<size_t> fill(lbm::NXCD, 0);
+        std::vector<lbm::BatchTile> spill;
+        for (int d : idx) {
+            int x = 0;
+            for (int k = 1; k < lbm::NXCD; ++k)
+                if (pos[k].size() - fill[k] > pos[x].size() - fill[x]) x = k;
+            for (const auto& t : per[d]) {
+                if (fill[x] < pos[x].size()) {
+                    const size_t p = pos[x][fill[x]++];
+                    out[p] = t;
+                    used[p] = 1;
+                } else {
+                    spill.push_back(t);
+                }
+            }
+        }
+        size_t k = 0;
+        for (size_t p = 0; p < total; ++p)
+            if (!used[p]) out[p] = spill[k++];
+    } else if (order == 2) {  // round robin: one tile of each domain in turn
         size_t k = 0;
         bool any = true;
         while (any) {
@@ -132,7 +166,7 @@ void set_parity(lbm_batch* b, int cur) {
 // launches queued on s before the call have read the old list) and drop the
 // captured graph.
 lbm_status upload_tiles(lbm_batch* b, hipStream_t s) {
-    std::vector<lbm::BatchTile> t = make_tiles(b, b->tile_y, b->order);
+    std::vector<lbm::BatchTile> t = make_tiles(b, b->tile_y, b->order, b->grid);
     if (t.size() > b->tiles_cap) return fail(LBM_EINVAL, "tile list exceeds its workspace area");
     b->ntiles = (int)t.size();
     HIP_TRY(hipMemcpyAsync(b->ws + b->off_tiles, t.data(), t.size() * sizeof(lbm::BatchTile), hipMemcpyHostToDevice, s));
@@ -155,6 +189,30 @@ lbm_status ensure_graph(lbm_batch* b) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
     b->graph_ok = true;
+    return LBM_OK;
+}
+
+// Autotuner results of this process, keyed by what the timing depends on:
+// the device's architecture, the batch's precision, force and gradient, and
+// its domain shapes in order (the tile list is built from them).
+struct TuneChoice {
+    int tile_y, order, grid;
+};
+std::mutex tune_mutex;
+std::map<std::string, TuneChoice> tune_cache;
+
+lbm_status tune_key(const lbm_batch* b, std::string* key) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%s|p%d|f%d|g%d|n%d|", prop.gcnArchName, b->prec, b->force, b->grad9, b->n);
+    *key = buf;
+    for (const auto* d : b->doms) {
+        snprintf(buf, sizeof(buf), "%dx%d%s,", d->p.nx, d->p.ny, d->p.walls ? "w" : "");
+        *key += buf;
+    }
     return LBM_OK;
 }
 
@@ -330,7 +388,7 @@ lbm_domain* lbm_batch_domain(lbm_batch* b, int32_t i) {
 
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t tile_y, int32_t order, int32_t grid, hipStream_t stream) {
     if (!b) return fail(LBM_EINVAL, "NULL batch");
-    if ((tile_y != 4 && tile_y != 8) || order < 0 || order > 2 || grid < 0)
+    if ((tile_y != 4 && tile_y != 8) || order < 0 || order > 3 || grid < 0)
         return fail(LBM_EINVAL, "schedule tile_y %d, order %d, grid %d", tile_y, order, grid);
     b->tile_y = tile_y;
     b->order = order;
@@ -352,6 +410,27 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* 
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t stream, char* report, size_t report_len) {
     if (!b || probe_steps < 1) return fail(LBM_EINVAL, "invalid arguments");
     HIP_TRY(hipStreamSynchronize(stream));
+    std::string key;
+    lbm_status kst = tune_key(b, &key);
+    if (kst != LBM_OK) return kst;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex);
+        auto it = tune_cache.find(key);
+        if (it != tune_cache.end()) {
+            b->tile_y = it->second.tile_y;
+            b->order = it->second.order;
+            b->grid = it->second.grid;
+            lbm_status st = upload_tiles(b, stream);
+            if (st != LBM_OK) return st;
+            if (report && report_len) {
+                char buf[128];
+                snprintf(buf, sizeof(buf), "{\"cached\": true, \"best\": \"ty%d_o%d_g%d\"}", b->tile_y, b->order, b->grid);
+                std::strncpy(report, buf, report_len - 1);
+                report[report_len - 1] = 0;
+            }
+            return LBM_OK;
+        }
+    }
     // snapshot every domain's current populations
     const int cur0 = b->cur;
     std::vector<size_t> soff(b->n);
@@ -367,11 +446,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
     HIP_TRY(hipEventCreate(&e1));
     const int tys[2] = {4, 8};
     const int grids[5] = {0, 256, 512, 1024, 2048};
+    constexpr int NORDER = 4;
     float best = 1e30f;
     int bt = b->tile_y, bo = b->order, bg = b->grid;
     std::string rep = "{";
     for (int ty : tys)
-        for (int order = 0; order < 3; ++order)
+        for (int order = 0; order < NORDER; ++order)
             for (int grid : grids) {
                 b->tile_y = ty;
                 b->order = order;
@@ -401,8 +481,12 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     char buf[128];
-    snprintf(buf, sizeof(buf), ", \"best\": \"ty%d_o%d_g%d\"}", bt, bo, bg);
+    snprintf(buf, sizeof(buf), ", \"cached\": false, \"best\": \"ty%d_o%d_g%d\"}", bt, bo, bg);
     rep += buf;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex);
+        tune_cache[key] = TuneChoice{bt, bo, bg};
+    }
     // restore the snapshot into the original parity and rebuild the potential fields
     set_parity(b, cur0);
     for (int i = 0; i < b->n; ++i) {
@@ -421,6 +505,11 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
         report[report_len - 1] = 0;
     }
     return LBM_OK;
+}
+
+void lbm_batch_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(tune_mutex);
+    tune_cache.clear();
 }
 
 lbm_status lbm_batch_check_finite(lbm_batch* b, int32_t* flags, hipStream_t stream) {

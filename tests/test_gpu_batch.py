@@ -86,7 +86,8 @@ def test_graph_and_separate_launches_agree():
         assert np.array_equal(a.domain(i).populations().cpu().numpy(), c.domain(i).populations().cpu().numpy()), i
 
 
-@pytest.mark.parametrize("tile_y,order,grid", [(4, 0, 0), (4, 1, 64), (8, 2, 0), (8, 0, 7), (8, 1, 1024)])
+@pytest.mark.parametrize("tile_y,order,grid", [(4, 0, 0), (4, 1, 64), (8, 2, 0), (8, 0, 7), (8, 1, 1024),
+                                                (4, 3, 0), (8, 3, 13), (4, 3, 2048)])
 def test_schedule_does_not_change_results(tile_y, order, grid):
     ps, rhos = sweep_params(8, 5, "f64", SHAPES)
     a = L.Batch(ps, [dev(r) for r in rhos])
@@ -100,16 +101,43 @@ def test_schedule_does_not_change_results(tile_y, order, grid):
 
 
 def test_autotune_restores_state_and_picks_a_candidate():
+    L.Batch.tune_cache_clear()
     ps, rhos = sweep_params(16, 9)
     a = L.Batch(ps, [dev(r) for r in rhos])
     a.step(3)
     rep = a.autotune(probe_steps=5)
-    assert "best" in rep and len(rep) == 31
+    assert rep["cached"] is False and len(rep) == 2 * 4 * 5 + 2
+    ty, o, g = (int(v.lstrip("tyog")) for v in rep["best"].split("_"))
+    assert a.schedule() == {"tile_y": ty, "order": o, "grid": g}
     a.step(10)
     ref = L.Batch(ps, [dev(r) for r in rhos])
     ref.step(13)
     for i in range(len(ps)):
         assert np.array_equal(a.domain(i).populations().cpu().numpy(), ref.domain(i).populations().cpu().numpy()), i
+
+
+def test_autotune_cache():
+    """A second batch of the same shapes takes the kept choice without timing;
+    other shapes, or a cleared cache, are timed again."""
+    L.Batch.tune_cache_clear()
+    ps, rhos = sweep_params(8, 21, "f64", SHAPES)
+    a = L.Batch(ps, [dev(r) for r in rhos])
+    first = a.autotune(probe_steps=3)
+    assert first["cached"] is False
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    b.set_schedule(8, 0, 7)
+    again = b.autotune(probe_steps=3)
+    assert again == {"cached": True, "best": first["best"]}
+    assert b.schedule() == a.schedule()
+    b.step(9)
+    ref = L.Batch(ps, [dev(r) for r in rhos])
+    ref.step(9)
+    for i in range(len(ps)):
+        assert np.array_equal(b.domain(i).populations().cpu().numpy(), ref.domain(i).populations().cpu().numpy()), i
+    other = L.Batch(ps[:7], [dev(r) for r in rhos[:7]])
+    assert other.autotune(probe_steps=3)["cached"] is False
+    L.Batch.tune_cache_clear()
+    assert b.autotune(probe_steps=3)["cached"] is False
 
 
 def test_schedule_change_after_steps_on_a_side_stream():
