@@ -533,6 +533,54 @@ def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.
     return out
 
 
+def adjoint_sizes(sizes, seg: int = 16, fwd_steps: int = 50):
+    """Per-step device cost of the reverse sweep against the forward step on
+    the differentiation workload scaled to n x n (CS droplet of radius 48 n /
+    256, T = 0.7 Tc, FP64, SC + HDM): forward step, recorded step (the
+    segment's recomputation, states stored) and reverse step inside a segment
+    of `seg` steps, each from HIP events.  (record + reverse) / forward is
+    what one forward step costs again in the checkpointed gradient, beside the
+    forward rollout itself."""
+    import torch
+
+    import paper_1712_06079_amd as L
+    out = []
+    for n in sizes:
+        p = L.Params(nx=n, ny=n, eos="cs", force="sc", a=1.0, b=4.0, R=1.0, k=0.04, tau=1.0)
+        tc, _ = L.critical(p)
+        p.T = 0.7 * tc
+        rv, rl, _ = L.maxwell(p, p.T)
+        d = L.Domain(p, torch.from_numpy(I.droplet(n, n, rv, rl, 48.0 * n / 256, 4.0)).cuda())
+        lam = torch.randn((9, n, n), dtype=torch.float64, device="cuda") * 1e-3
+        lam2 = torch.empty_like(lam)
+        grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+        ws = d.adjoint_workspace()
+        states = d.new_states(seg + 1)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        d.step(20)
+        d.record(states, seg)
+        d.adjoint_steps(states, seg, lam, lam2, grad, ws)
+        torch.cuda.synchronize()
+        ev[0].record()
+        d.step(fwd_steps)
+        ev[1].record()
+        d.record(states, seg)
+        ev[2].record()
+        d.adjoint_steps(states, seg, lam, lam2, grad, ws)
+        ev[3].record()
+        torch.cuda.synchronize()
+        f, r, a = (ev[0].elapsed_time(ev[1]) / fwd_steps, ev[1].elapsed_time(ev[2]) / seg,
+                   ev[2].elapsed_time(ev[3]) / seg)
+        out.append({"n": n, "ms_forward": round(f, 4), "ms_record": round(r, 4), "ms_reverse": round(a, 4),
+                    "reverse_over_forward": round(a / f, 3), "record_plus_reverse_over_forward": round((r + a) / f, 3),
+                    "finite": bool(torch.isfinite(lam).all())})
+        print(f"[bench] adjoint {n}^2: forward {f:.4f} ms, record {r:.4f}, reverse {a:.4f} "
+              f"(reverse/forward {a / f:.2f})", file=sys.stderr, flush=True)
+        del d, lam, lam2, ws, states
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_cost(steps: int, every: int, seed: int = 2024):
     """The differentiation workload: 256 x 256 CS droplet R = 48 (W = 4) at
     T = 0.7 Tc, FP64, tau = 1, SC + HDM; J = sum (rho_n - rho_target)^2 with
@@ -966,6 +1014,8 @@ def main():
                     help="steps timed right after the headline window on the same domain (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10000, help="batched-sweep steps (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5000, help="differentiated rollout steps (0 = skip)")
+    ap.add_argument("--adjoint-sizes", type=int, nargs="*", default=[256, 1024, 4096],
+                    help="lattice sides of the per-step reverse-sweep cost curve (none = skip)")
     ap.add_argument("--fig5-steps", type=int, default=60000, help="steps of the coexistence comparison (0 = skip)")
     ap.add_argument("--no-sigma", dest="sigma", action="store_false", help="skip the surface-tension report")
     ap.add_argument("--splash-re", type=float, nargs="*", default=[40.0, 100.0, 173.0],
@@ -1027,6 +1077,7 @@ def main():
         adjoint = adjoint_cost(args.adjoint_steps, 70)
         print(f"[bench] adjoint/forward step {adjoint['adjoint_over_forward']}, gradient/forward "
               f"{adjoint['gradient_over_forward']}", file=sys.stderr, flush=True)
+    adj_sizes = adjoint_sizes(args.adjoint_sizes) if args.adjoint_sizes else None
     droplet = droplet_report(args.droplet_steps) if args.droplet_steps > 0 else None
     slab = slab_precision(2000) if args.droplet_steps > 0 else None
     long_cmp = long_run_comparison(args.long_steps) if args.long_steps > 0 and args.workload == "c5" else None
@@ -1068,6 +1119,8 @@ def main():
         line["splash"] = splash
     if adjoint:
         line["adjoint"] = adjoint
+    if adj_sizes:
+        line["adjoint_sizes"] = adj_sizes
     if droplet:
         line["droplet_c2"] = droplet
     if slab:

@@ -160,25 +160,19 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
 // parameter partials per workgroup (fixed order).
 template <int FORCE, int TY>
 __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
-    __shared__ Cross<double, TY> sx;   // row bar of a_x (col bar unused)
-    __shared__ Cross<double, TY> sy;   // col bar of a_y (row bar unused)
+    using C = Cross<double, TY>;
+    __shared__ double rowx[TY][C::RW];   // row bar of a_x
+    __shared__ double coly[C::CH][BX];   // column bar of a_y
     __shared__ double red[2][NT / BX];
     const StepArgs<double>& a = A.s;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
-    using C = Cross<double, TY>;
-    stage_lds<TY * C::RW, 8>(&sx.row[0][0], [&](int i) {
-        const int r = i / C::RW, c = i - r * C::RW;
-        const int y = min(y0 + r, a.ny - 1);
-        const int xw = wrap(x0 - C::J + c, a.nx);
-        return A.ax[(long)y * pitch + xw];
+    stage_lds_rc<TY * C::RW, C::RW, 8>(&rowx[0][0], [&](int r, int c) {
+        return A.ax[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - C::J + c, a.nx), pitch)];
     });
-    stage_lds<C::CH * BX, 8>(&sy.col[0][0], [&](int i) {
-        const int r = i / BX, c = i - r * BX;
-        const int yw = wrap(y0 - C::J + r, a.ny);
-        const int xx = min(x0 + c, a.nx - 1);
-        return A.ay[(long)yw * pitch + xx];
+    stage_lds_rc<C::CH * BX, BX, 8>(&coly[0][0], [&](int r, int c) {
+        return A.ay[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)];
     });
     __syncthreads();
     constexpr int J = C::J;
@@ -188,8 +182,8 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         const int y = y0 + r;
         if (y >= a.ny) break;
         double dxa = 0, dya = 0;
-        for (int j = 1; j <= a.tx; ++j) dxa += a.tab->dx[j - 1] * (sx.row[r][J + lx + j] - sx.row[r][J + lx - j]);
-        for (int j = 1; j <= a.ty; ++j) dya += a.tab->dy[j - 1] * (sy.col[J + r + j][lx] - sy.col[J + r - j][lx]);
+        for (int j = 1; j <= a.tx; ++j) dxa += a.tab->dx[j - 1] * (rowx[r][J + lx + j] - rowx[r][J + lx - j]);
+        for (int j = 1; j <= a.ty; ++j) dya += a.tab->dy[j - 1] * (coly[J + r + j][lx] - coly[J + r - j][lx]);
         if (x >= a.nx) continue;
         const long op = (long)y * pitch + x;
         double ub;

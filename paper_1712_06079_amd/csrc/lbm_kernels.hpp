@@ -157,21 +157,48 @@ __device__ inline void stage_lds(double* __restrict__ dst, Src src) {
     }
 }
 
+// stage_lds over an array of rows of W elements: src(r, c) receives the row
+// and column of element i, stepped from one division per call.
+template <int N, int W, int B, typename Src>
+__device__ inline void stage_lds_rc(double* __restrict__ dst, Src src) {
+    constexpr int PER = (N + NT - 1) / NT;
+    constexpr int DR = NT / W, DC = NT - DR * W;
+    const int tid = threadIdx.x;
+    int r = tid / W, c = tid - r * W;
+#pragma unroll
+    for (int j0 = 0; j0 < PER; j0 += B) {
+        double v[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (j0 + j < PER && tid + (j0 + j) * NT < N) v[j] = src(r, c);
+            r += DR;
+            c += DC;
+            if (c >= W) {
+                c -= W;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int i = tid + (j0 + j) * NT;
+            if (j0 + j < PER && i < N) dst[i] = v[j];
+        }
+    }
+}
+
+// Offset of lattice cell (x, y) in a potential or scratch plane of row pitch
+// `pitch` (fewer than 2^31 elements; sides at most 2^21, so 24-bit products).
+__device__ inline unsigned plane_at(int y, int x, int pitch) { return (unsigned)(__mul24(y, pitch) + x); }
+
 template <typename Real, int TY, typename P>
 __device__ inline void stage_cross(Cross<Real, TY>& s, const P* __restrict__ phi, int x0, int y0, int nx,
                                    int ny, int pitch, int walls = 0) {
     using C = Cross<Real, TY>;
-    stage_lds<TY * C::RW, 8>(&s.row[0][0], [&](int i) {
-        const int r = i / C::RW, c = i - r * C::RW;
-        const int y = min(y0 + r, ny - 1);
-        const int x = wrap(x0 - C::J + c, nx);
-        return (double)phi[(long)y * pitch + x];
+    stage_lds_rc<TY * C::RW, C::RW, 8>(&s.row[0][0], [&](int r, int c) {
+        return (double)phi[plane_at(min(y0 + r, ny - 1), wrap_fast(x0 - C::J + c, nx), pitch)];
     });
-    stage_lds<C::CH * BX, 8>(&s.col[0][0], [&](int i) {
-        const int r = i / BX, c = i - r * BX;
-        const int y = ymap(y0 - C::J + r, ny, walls);
-        const int x = min(x0 + c, nx - 1);
-        return (double)phi[(long)y * pitch + x];
+    stage_lds_rc<C::CH * BX, BX, 8>(&s.col[0][0], [&](int r, int c) {
+        return (double)phi[plane_at(ymap_fast(y0 - C::J + r, ny, walls), min(x0 + c, nx - 1), pitch)];
     });
 }
 
@@ -189,9 +216,8 @@ struct Block9 {
 
 template <int TY, typename P>
 __device__ inline void stage_block9(Block9<TY>& b, const P* __restrict__ phi, int x0, int y0, int nx, int ny, int pitch) {
-    stage_lds<(TY + 2) * Block9<TY>::W, 8>(&b.v[0][0], [&](int i) {
-        const int r = i / Block9<TY>::W, c = i - r * Block9<TY>::W;
-        return (double)phi[(long)wrap(y0 - 1 + r, ny) * pitch + wrap(x0 - 1 + c, nx)];
+    stage_lds_rc<(TY + 2) * Block9<TY>::W, Block9<TY>::W, 8>(&b.v[0][0], [&](int r, int c) {
+        return (double)phi[plane_at(wrap_fast(y0 - 1 + r, ny), wrap_fast(x0 - 1 + c, nx), pitch)];
     });
 }
 
