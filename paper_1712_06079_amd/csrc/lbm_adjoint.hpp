@@ -72,6 +72,20 @@ __device__ inline void dA(int i, double ir, double mx, double my, double& dr, do
     dmy = w * (3.0 * double(ey(i)) + (9.0 * em * double(ey(i)) - 3.0 * my) * ir);
 }
 
+// sum_{j=1..taps} c_j (op(base[j stride]) - op(base[-j stride])), in that
+// order; unrolled when the line keeps the full radius J (every long axis).
+template <int J, typename Op>
+__device__ inline double dline(const double* __restrict__ c, const double* base, int stride, int taps, Op op) {
+    double s = 0.0;
+    if (taps == J) {
+#pragma unroll
+        for (int j = 1; j <= J; ++j) s += c[j - 1] * (op(base[j * stride]) - op(base[-j * stride]));
+    } else {
+        for (int j = 1; j <= taps; ++j) s += c[j - 1] * (op(base[j * stride]) - op(base[-j * stride]));
+    }
+    return s;
+}
+
 struct AdjArgs {
     StepArgs<double> s;             // f_in = state f_t, phi_in = phi(f_t), tables
     const double* __restrict__ lam_next;  // [9][ny][nx]
@@ -102,15 +116,9 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
         const int y = y0 + r;
         if (y >= a.ny) break;
         const double pc = s.row[r][J + lx];
-        double gx = 0, gy = 0;
-        for (int j = 1; j <= a.tx; ++j) {
-            const double p = s.row[r][J + lx + j], m = s.row[r][J + lx - j];
-            gx += a.tab->dx[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
-        }
-        for (int j = 1; j <= a.ty; ++j) {
-            const double p = s.col[J + r + j][lx], m = s.col[J + r - j][lx];
-            gy += a.tab->dy[j - 1] * (FORCE == FORCE_ZC ? p - m : fabs(p) - fabs(m));
-        }
+        auto opf = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
+        const double gx = dline<J>(a.tab->dx, &s.row[r][J + lx], 1, a.tx, opf);
+        const double gy = dline<J>(a.tab->dy, &s.col[J + r][lx], BX, a.ty, opf);
         if (x >= a.nx) continue;
         const double Fx = FORCE == FORCE_ZC ? -gx : -2.0 * pc * gx;
         const double Fy = FORCE == FORCE_ZC ? -gy : -2.0 * pc * gy;
@@ -181,9 +189,9 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
         const int y = y0 + r;
         if (y >= a.ny) break;
-        double dxa = 0, dya = 0;
-        for (int j = 1; j <= a.tx; ++j) dxa += a.tab->dx[j - 1] * (rowx[r][J + lx + j] - rowx[r][J + lx - j]);
-        for (int j = 1; j <= a.ty; ++j) dya += a.tab->dy[j - 1] * (coly[J + r + j][lx] - coly[J + r - j][lx]);
+        auto id = [](double v) { return v; };
+        const double dxa = dline<J>(a.tab->dx, &rowx[r][J + lx], 1, a.tx, id);
+        const double dya = dline<J>(a.tab->dy, &coly[J + r][lx], BX, a.ty, id);
         if (x >= a.nx) continue;
         const long op = (long)y * pitch + x;
         double ub;

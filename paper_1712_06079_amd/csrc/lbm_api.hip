@@ -532,9 +532,12 @@ lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride
 }
 
 namespace {
-// Rows per tile of the reverse kernels: 8, or 4 when 8-row tiles would leave
-// compute units idle (small lattices).  The partials buffer is sized for 4.
+// Rows per tile of the reverse kernels: 16 where that still gives two tiles
+// per compute unit (a taller tile stages its +-R column halo for more rows),
+// else 8, or 4 when 8-row tiles would leave compute units idle (small
+// lattices).  The partials buffer is sized for 4.
 int adj_ty(const lbm_domain* d) {
+    if ((long)d->nxb * ((d->p.ny + 15) / 16) >= 2L * d->ncu) return 16;
     return (long)d->nxb * ((d->p.ny + 7) / 8) >= d->ncu ? 8 : 4;
 }
 struct AdjLayout {
@@ -607,10 +610,11 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     using ZC = std::integral_constant<int, lbm::FORCE_ZC>;
     using T4 = std::integral_constant<int, 4>;
     using T8 = std::integral_constant<int, 8>;
+    using T16 = std::integral_constant<int, 16>;
     if (d->p.force == LBM_FORCE_SC) {
-        if (ty == 8) launch(SC(), T8()); else launch(SC(), T4());
+        if (ty == 16) launch(SC(), T16()); else if (ty == 8) launch(SC(), T8()); else launch(SC(), T4());
     } else {
-        if (ty == 8) launch(ZC(), T8()); else launch(ZC(), T4());
+        if (ty == 16) launch(ZC(), T16()); else if (ty == 8) launch(ZC(), T8()); else launch(ZC(), T4());
     }
     HIP_TRY(hipGetLastError());
     return LBM_OK;
