@@ -81,7 +81,8 @@ def test_explicit_hdm_row_matches_chasing_solve(n, prec):
 
 def test_invalid_parameters_rejected_without_device():
     lib = L.library()
-    for bad in (dict(nx=4), dict(ny=3), dict(tau=0.5), dict(T=-1.0), dict(k=0.0), dict(eos="vdw", a=-1.0)):
+    for bad in (dict(nx=4), dict(ny=3), dict(tau=0.5), dict(T=-1.0), dict(k=0.0), dict(eos="vdw", a=-1.0),
+                dict(nx=(1 << 21) + 1, ny=5), dict(nx=5, ny=(1 << 21) + 1), dict(nx=1 << 16, ny=(1 << 15) + 1)):
         p = L.Params(**bad)
         nb = C.c_size_t()
         st = lib.lbm_workspace_bytes(C.byref(p.c()), C.byref(nb))
@@ -89,6 +90,15 @@ def test_invalid_parameters_rejected_without_device():
         h = C.c_void_p()
         st = lib.lbm_init(C.byref(p.c()), None, 0, None, None, None, None, C.byref(h))
         assert st == 1 and lib.lbm_last_error(), bad
+
+
+def test_largest_sides_accepted():
+    """Sides up to 2^21 and nx ny up to 2^31 pass validation (the kernels'
+    24-bit index arithmetic holds there)."""
+    lib = L.library()
+    for nx, ny in ((1 << 21, 5), (5, 1 << 21), (1 << 16, 1 << 15), (1 << 21, 1 << 10)):
+        nb = C.c_size_t()
+        assert lib.lbm_workspace_bytes(C.byref(L.Params(nx=nx, ny=ny).c()), C.byref(nb)) == 0, (nx, ny)
 
 
 def test_workspace_size_formula():
