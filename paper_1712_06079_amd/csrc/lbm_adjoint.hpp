@@ -19,6 +19,11 @@
 // Pass 1 (k_adj_local) does everything local to a cell and writes the planes
 // a_x, a_y, U_bar_local and rho; pass 2 (k_adj_nonlocal) applies D to the a
 // planes from an LDS cross, finishes U_bar and adds the density term.
+// On a y axis longer than 2R + 1 both y derivatives are column marches
+// instead (k_adj_dy, geometric form): one before pass 1 leaves D_y of the
+// potential operand in the rho plane (pass 1 reads it at its own cell before
+// storing rho there), one between the passes adds the D_y a_y term of U_bar
+// to the U_bar_local plane, and the passes stage only their row bars.
 #pragma once
 
 #include "lbm_kernels.hpp"
@@ -99,18 +104,156 @@ struct AdjArgs {
     AdjEos e;
 };
 
+// Column march of Eq. 20 along y in geometric form (the march kernel's y
+// machinery without its LDS): one lane per lattice column, a workgroup takes
+// four 64-column strips over one chunk of rows and walks down it in blocks of
+// TY = 8 rows.  The lane keeps the window of rows yb-4 .. yb+TY+3 (operand
+// values, op applied), the forward sum Lt and the block sums W_1 .. W_NB of
+// the rows ahead in registers; per block it loads the window's TY new rows and
+// the TY rows NB blocks ahead.  Differences, recursions and the Horner sum
+// over the block sums are those of the march kernel (see stencil_recursive
+// for the form).  Needs ny > 2R + 1 and ny > (NB + 2) TY + 3.
+//   MODE 0: out = rho plane <- D_y op(phi)  (op = |.| for SC, identity for ZC)
+//   MODE 1: U_bar_local plane += c D_y a_y, c = 1 (ZC) or -s / (2 Phi) (SC).
+template <int FORCE, int MODE>
+__global__ void __launch_bounds__(NT) k_adj_dy(AdjArgs A, int nchunk) {
+    constexpr int R = Radius<double>::value, TY = 8;
+    constexpr int NB = (R - 3 + TY - 1) / TY;
+    const StepArgs<double>& a = A.s;
+    const int strip = blockIdx.x * (NT / BX) + (int)(threadIdx.x >> 6);
+    if (strip >= a.nxb) return;  // whole wavefronts; no barrier below
+    const int xl = strip * BX + (int)(threadIdx.x & (BX - 1));
+    const bool own = xl < a.nx;
+    const int x = own ? xl : a.nx - 1;
+    const int ny = a.ny, pitch = a.nxb * BX;
+    const int ys = (int)((long)blockIdx.y * ny / nchunk), ye = (int)((long)(blockIdx.y + 1) * ny / nchunk);
+    const double* __restrict__ src = MODE == 0 ? static_cast<const double*>(a.phi_in) : A.ay;
+    // every row index below lies in [ys - R, ye + (NB + 2) TY + 3), within one period
+    auto at = [&](int y) {
+        const int yw = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        const double v = src[plane_at(yw, x, pitch)];
+        return (MODE == 0 && FORCE != FORCE_ZC) ? fabs(v) : v;
+    };
+    const double rr = a.rr, rr3 = a.rr3, rr4 = a.rr4, rd1 = a.rd1, rd2 = a.rd2, rK = a.rK;
+    double rT = 1.0;
+#pragma unroll
+    for (int j = 0; j < TY; ++j) rT *= rr;
+    // W = sum_n r^n t_n, t_n = r^4 (u_{n+1} - u_n) over the rows u0, p[0 .. TY-1]
+    auto block_sum = [&](double u0, const double (&p)[TY]) {
+        double w = 0.0;
+#pragma unroll
+        for (int n = TY - 1; n >= 0; --n) w = fma(rr, w, rr4 * (p[n] - (n == 0 ? u0 : p[n - 1])));
+        return w;
+    };
+    // prologue: forward sum over rows ys-R .. ys-4, block sums of block 0
+    // (rows ys+3+TY .. ys+3+(NB+1)TY), the window of block 0
+    double l = 0.0;
+    {
+        double prev = at(ys - R);
+#pragma unroll
+        for (int m = 1; m <= R - 4; ++m) {
+            const double u = at(ys - R + m);
+            l = fma(rr, l, rr4 * (u - prev));
+            prev = u;
+        }
+    }
+    double W[NB];
+    double uprev = at(ys + 3 + TY);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double p[TY];
+#pragma unroll
+        for (int n = 0; n < TY; ++n) p[n] = at(ys + 3 + TY + j * TY + n + 1);
+        W[j] = block_sum(uprev, p);
+        uprev = p[TY - 1];
+    }
+    double win[TY + 8];
+#pragma unroll
+    for (int j = 0; j < TY + 8; ++j) win[j] = at(ys - 4 + j);
+
+    for (int yb = ys; yb < ye; yb += TY) {
+        // loads of the next block: its new window rows, the rows NB blocks ahead
+        double nw[TY], far[TY];
+#pragma unroll
+        for (int j = 0; j < TY; ++j) nw[j] = at(yb + TY + 4 + j);
+#pragma unroll
+        for (int j = 0; j < TY; ++j) far[j] = at(yb + TY + 4 + NB * TY + j);
+        // outputs of rows yb .. yb+TY-1
+        double Lt[TY], g[TY];
+#pragma unroll
+        for (int o = 0; o < TY; ++o) {
+            l = fma(rr, l, rr4 * (win[o + 1] - win[o]));
+            Lt[o] = l;
+        }
+        double q = W[NB - 1];
+#pragma unroll
+        for (int j = NB - 2; j >= 0; --j) q = fma(rT, q, W[j]);
+#pragma unroll
+        for (int o = TY - 1; o >= 0; --o) {
+            q = fma(rr, q, rr4 * (win[o + 8] - win[o + 7]));
+            const int w = o + 4;
+            g[o] = rd1 * (win[w + 1] - win[w - 1]) + rd2 * (win[w + 2] - win[w - 2]) +
+                   rK * (rr3 * (win[w + 3] - win[w - 3]) + q + Lt[o]);
+        }
+        if (own) {
+#pragma unroll
+            for (int o = 0; o < TY; ++o) {
+                const int y = yb + o;
+                if (y < ye) {
+                    const unsigned c = plane_at(y, x, pitch);
+                    if (MODE == 0) {
+                        A.rho[c] = g[o];
+                    } else if (FORCE == FORCE_ZC) {
+                        A.ubl[c] += g[o];
+                    } else {
+                        const double ph = static_cast<const double*>(a.phi_in)[c];
+                        const double sgn = ph < 0.0 ? -1.0 : 1.0;
+                        A.ubl[c] += sgn / (2.0 * fabs(ph)) * (-g[o]);
+                    }
+                }
+            }
+        }
+        // advance: block sums, window
+#pragma unroll
+        for (int j = 0; j < NB - 1; ++j) W[j] = W[j + 1];
+        W[NB - 1] = block_sum(uprev, far);
+        uprev = far[TY - 1];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) win[j] = win[j + TY];
+#pragma unroll
+        for (int j = 0; j < TY; ++j) win[8 + j] = nw[j];
+    }
+}
+
+// Row bar alone (the column march supplies the y derivatives).
+template <int TY>
+struct RowBar {
+    static constexpr int J = Cross<double, TY>::J;
+    static constexpr int RW = Cross<double, TY>::RW;
+    double row[TY][RW];
+};
+
 // Pass 1: per 64 x TY tile, stage phi_t, recompute F and D Phi, pull lam_next,
-// local adjoint of collision and force.
-template <int FORCE, int TY>
+// local adjoint of collision and force.  GY: D_y of the potential operand is
+// read from the rho plane (k_adj_dy) and only the row bar is staged.
+template <int FORCE, int TY, bool GY = false>
 __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
-    __shared__ Cross<double, TY> s;
+    using Bars = typename std::conditional<GY, RowBar<TY>, Cross<double, TY>>::type;
+    __shared__ Bars s;
     const StepArgs<double>& a = A.s;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
-    stage_cross<double, TY>(s, static_cast<const double*>(a.phi_in), x0, y0, a.nx, a.ny, pitch);
+    if constexpr (GY) {
+        const double* phi = static_cast<const double*>(a.phi_in);
+        stage_lds_rc<TY * Bars::RW, Bars::RW, 8>(&s.row[0][0], [&](int r, int c) {
+            return phi[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - Bars::J + c, a.nx), pitch)];
+        });
+    } else {
+        stage_cross<double, TY>(s, static_cast<const double*>(a.phi_in), x0, y0, a.nx, a.ny, pitch);
+    }
     __syncthreads();
-    constexpr int J = Cross<double, TY>::J;
+    constexpr int J = Bars::J;
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
     for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
         const int y = y0 + r;
@@ -118,8 +261,10 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
         const double pc = s.row[r][J + lx];
         auto opf = [](double v) { return FORCE == FORCE_ZC ? v : fabs(v); };
         const double gx = dline<J>(a.tab->dx, &s.row[r][J + lx], 1, a.tx, opf);
-        const double gy = dline<J>(a.tab->dy, &s.col[J + r][lx], BX, a.ty, opf);
+        double gy = 0.0;
+        if constexpr (!GY) gy = dline<J>(a.tab->dy, &s.col[J + r][lx], BX, a.ty, opf);
         if (x >= a.nx) continue;
+        if constexpr (GY) gy = A.rho[plane_at(y, x, pitch)];  // this cell's rho is stored there below
         const double Fx = FORCE == FORCE_ZC ? -gx : -2.0 * pc * gx;
         const double Fy = FORCE == FORCE_ZC ? -gy : -2.0 * pc * gy;
         double f[Q];
@@ -166,11 +311,11 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
 
 // Pass 2: D applied to the a planes (staged like phi), U_bar, density term,
 // parameter partials per workgroup (fixed order).
-template <int FORCE, int TY>
+template <int FORCE, int TY, bool GY = false>
 __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
     using C = Cross<double, TY>;
-    __shared__ double rowx[TY][C::RW];   // row bar of a_x
-    __shared__ double coly[C::CH][BX];   // column bar of a_y
+    __shared__ double rowx[TY][C::RW];                 // row bar of a_x
+    __shared__ double coly[GY ? 1 : C::CH][BX];        // column bar of a_y (GY: unused)
     __shared__ double red[2][NT / BX];
     const StepArgs<double>& a = A.s;
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
@@ -179,9 +324,11 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
     stage_lds_rc<TY * C::RW, C::RW, 8>(&rowx[0][0], [&](int r, int c) {
         return A.ax[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - C::J + c, a.nx), pitch)];
     });
-    stage_lds_rc<C::CH * BX, BX, 8>(&coly[0][0], [&](int r, int c) {
-        return A.ay[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)];
-    });
+    if constexpr (!GY) {
+        stage_lds_rc<C::CH * BX, BX, 8>(&coly[0][0], [&](int r, int c) {
+            return A.ay[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)];
+        });
+    }
     __syncthreads();
     constexpr int J = C::J;
     const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
@@ -191,11 +338,19 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         if (y >= a.ny) break;
         auto id = [](double v) { return v; };
         const double dxa = dline<J>(a.tab->dx, &rowx[r][J + lx], 1, a.tx, id);
-        const double dya = dline<J>(a.tab->dy, &coly[J + r][lx], BX, a.ty, id);
+        const double dya = GY ? 0.0 : dline<J>(a.tab->dy, &coly[(GY ? 0 : J + r)][lx], BX, a.ty, id);
         if (x >= a.nx) continue;
         const long op = (long)y * pitch + x;
         double ub;
-        if (FORCE == FORCE_ZC) {
+        if (GY) {  // the D_y term is already in the U_bar_local plane (k_adj_dy)
+            if (FORCE == FORCE_ZC) {
+                ub = A.ubl[op] + dxa;
+            } else {
+                const double ph = static_cast<const double*>(a.phi_in)[op];
+                const double sgn = ph < 0.0 ? -1.0 : 1.0;
+                ub = A.ubl[op] + sgn / (2.0 * fabs(ph)) * (-dxa);
+            }
+        } else if (FORCE == FORCE_ZC) {
             ub = dxa + dya;
         } else {
             const double ph = static_cast<const double*>(a.phi_in)[op];

@@ -540,6 +540,22 @@ int adj_ty(const lbm_domain* d) {
     if ((long)d->nxb * ((d->p.ny + 15) / 16) >= 2L * d->ncu) return 16;
     return (long)d->nxb * ((d->p.ny + 7) / 8) >= d->ncu ? 8 : 4;
 }
+// Chunks of the column march that takes the y derivatives of the reverse
+// step (k_adj_dy), or 0 where the tiles keep them.  The march needs the
+// geometric form along y (ny > 2R + 1, which also gives ny > (NB + 2) 8 + 3).
+// Kernel variant 3 (marching) always takes it there, variants 1 and 2 (tiles)
+// never; the automatic choice takes it once chunks of at least 64 rows give
+// every compute unit two wavefronts (at 1024^2, one per unit, the tiles are
+// faster: 0.135 against 0.146 ms).  About eight wavefronts per compute unit.
+int adj_dy_chunks(const lbm_domain* d) {
+    constexpr int R = lbm::Radius<double>::value;
+    if (d->p.grad != LBM_GRAD_HDM || d->p.ny <= 2 * R + 1 || d->variant == 1 || d->variant == 2) return 0;
+    const long most = std::max(1, d->p.ny / 64);
+    if (d->variant == 0 && (long)d->nxb * (d->p.ny / 64) < 2L * d->ncu) return 0;
+    const long want = (8L * d->ncu + d->nxb - 1) / d->nxb;
+    return (int)std::max(1L, std::min(most, want));
+}
+
 struct AdjLayout {
     size_t plane, f, part, total;
 };
@@ -601,10 +617,19 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     A.e.kR = d->p.k * d->p.R;
     const int ty = adj_ty(d);
     dim3 grid(d->nxb, (d->p.ny + ty - 1) / ty);
+    const int nchunk = adj_dy_chunks(d);
+    const dim3 gdy((d->nxb + lbm::NT / lbm::BX - 1) / (lbm::NT / lbm::BX), nchunk > 0 ? nchunk : 1);
     auto launch = [&](auto force, auto tyc) {
         constexpr int F = decltype(force)::value, TY = decltype(tyc)::value;
-        hipLaunchKernelGGL((lbm::k_adj_local<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
-        hipLaunchKernelGGL((lbm::k_adj_nonlocal<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
+        if (nchunk > 0) {  // y derivatives by column marches
+            hipLaunchKernelGGL((lbm::k_adj_dy<F, 0>), gdy, dim3(lbm::NT), 0, stream, A, nchunk);
+            hipLaunchKernelGGL((lbm::k_adj_local<F, TY, true>), grid, dim3(lbm::NT), 0, stream, A);
+            hipLaunchKernelGGL((lbm::k_adj_dy<F, 1>), gdy, dim3(lbm::NT), 0, stream, A, nchunk);
+            hipLaunchKernelGGL((lbm::k_adj_nonlocal<F, TY, true>), grid, dim3(lbm::NT), 0, stream, A);
+        } else {
+            hipLaunchKernelGGL((lbm::k_adj_local<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
+            hipLaunchKernelGGL((lbm::k_adj_nonlocal<F, TY>), grid, dim3(lbm::NT), 0, stream, A);
+        }
     };
     using SC = std::integral_constant<int, lbm::FORCE_SC>;
     using ZC = std::integral_constant<int, lbm::FORCE_ZC>;

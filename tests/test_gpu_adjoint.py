@@ -36,15 +36,20 @@ def case(eos, force, nx, ny, tr=0.7, tau=0.8, seed=3):
     return po, rho0, rv, rl
 
 
-@pytest.mark.parametrize("eos,force,nx,ny", [("cs", "sc", 70, 37), ("vdw", "zc", 64, 64), ("pr", "sc", 33, 80),
-                                             ("rks", "zc", 130, 17), ("rk", "sc", 96, 96), ("cs", "zc", 5, 9)])
-def test_adjoint_step_matches_oracle(eos, force, nx, ny):
+@pytest.mark.parametrize("eos,force,nx,ny,variant", [
+    ("cs", "sc", 70, 37, 0), ("vdw", "zc", 64, 64, 0), ("pr", "sc", 33, 80, 0), ("rks", "zc", 130, 17, 0),
+    ("rk", "sc", 96, 96, 0), ("cs", "zc", 5, 9, 0),
+    # y derivatives by the column march: one chunk, ragged rows and columns, several chunks
+    ("pr", "sc", 33, 80, 3), ("rk", "sc", 96, 96, 3), ("cs", "zc", 40, 120, 3), ("vdw", "sc", 70, 203, 3),
+    ("cs", "zc", 64, 512, 3), ("rks", "sc", 130, 300, 3)])
+def test_adjoint_step_matches_oracle(eos, force, nx, ny, variant):
     """One reverse step at a non-trivial state with a random cotangent."""
     po, rho0, _, _ = case(eos, force, nx, ny)
     f_t = O.run(po, O.init(po, rho0), 5)
     lam_next = np.random.default_rng(nx * ny).standard_normal(f_t.shape)
     ref_lam, ref_grad = O.adjoint_step(po, f_t, lam_next)
     d = L.Domain(lib_params(po), dev(rho0))
+    d.set_kernel(variant, 0)
     d.set_populations(dev(f_t))
     st = d.new_states(1)
     d.save_state(st[0])
@@ -111,6 +116,32 @@ def test_rollout_gradient_finite_differences():
     assert abs(g.grad.item() / fd_g - 1) < 1e-5, (g.grad.item(), fd_g)
     assert abs(T.grad.item() / fd_T - 1) < 1e-5, (T.grad.item(), fd_T)
     assert abs(ad_r / fd_r - 1) < 1e-5, (ad_r, fd_r)
+
+
+def test_column_march_and_tiles_agree_at_full_width():
+    """A 2048 x 1024 reverse step with the y derivatives by column marches
+    (the automatic choice on this lattice) and by tiles, both against the
+    oracle's reverse step and against each other."""
+    po, rho0, _, _ = case("cs", "sc", 2048, 1024, tau=1.0)
+    f_t = O.run(po, O.init(po, rho0), 2)
+    lam_next = np.random.default_rng(11).standard_normal(f_t.shape)
+    ref_lam, ref_grad = O.adjoint_step(po, f_t, lam_next)
+    out = {}
+    for variant in (0, 2):
+        d = L.Domain(lib_params(po), dev(rho0))
+        d.set_kernel(variant, 0)
+        d.set_populations(dev(f_t))
+        st = d.new_states(1)
+        d.save_state(st[0])
+        lam = torch.empty((9, 1024, 2048), dtype=torch.float64, device="cuda")
+        grad = torch.zeros(2, dtype=torch.float64, device="cuda")
+        d.adjoint_step(st[0], dev(lam_next), lam, grad, d.adjoint_workspace())
+        out[variant] = (lam.cpu().numpy(), grad.cpu().numpy())
+    scale = np.abs(ref_lam).max()
+    for variant, (lam, g) in out.items():
+        assert np.max(np.abs(lam - ref_lam)) < 1e-11 * scale, (variant, np.max(np.abs(lam - ref_lam)) / scale)
+        assert np.all(np.abs(g - ref_grad) < 1e-10 * np.maximum(1.0, np.abs(ref_grad))), (variant, g, ref_grad)
+    assert np.max(np.abs(out[0][0] - out[2][0])) < 1e-12 * scale
 
 
 def test_adjoint_unsupported_variants():
