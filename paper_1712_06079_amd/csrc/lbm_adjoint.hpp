@@ -225,6 +225,49 @@ __global__ void __launch_bounds__(NT) k_adj_dy(AdjArgs A, int nchunk) {
     }
 }
 
+// Two bars staged with every load in flight at once (rows of WR and WC
+// elements; src(r, c) as in stage_lds_rc).  The 4-row tiles of small
+// lattices use it: there the reverse passes are latency-bound, and staging in
+// batches of 8 loads per thread took three memory round trips per tile.
+template <int NR, int WR, int NC, int WC, typename SrcR, typename SrcC>
+__device__ inline void stage_two(double* __restrict__ dr, SrcR sr, double* __restrict__ dc, SrcC sc) {
+    constexpr int PR = (NR + NT - 1) / NT, PC = (NC + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    double vr[PR], vc[PC];
+    {
+        int r = tid / WR, c = tid - r * WR;
+#pragma unroll
+        for (int j = 0; j < PR; ++j) {
+            if (tid + j * NT < NR) vr[j] = sr(r, c);
+            r += NT / WR;
+            c += NT % WR;
+            if (c >= WR) {
+                c -= WR;
+                ++r;
+            }
+        }
+    }
+    {
+        int r = tid / WC, c = tid - r * WC;
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+            if (tid + j * NT < NC) vc[j] = sc(r, c);
+            r += NT / WC;
+            c += NT % WC;
+            if (c >= WC) {
+                c -= WC;
+                ++r;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PR; ++j)
+        if (tid + j * NT < NR) dr[tid + j * NT] = vr[j];
+#pragma unroll
+    for (int j = 0; j < PC; ++j)
+        if (tid + j * NT < NC) dc[tid + j * NT] = vc[j];
+}
+
 // Row bar alone (the column march supplies the y derivatives).
 template <int TY>
 struct RowBar {
@@ -244,18 +287,45 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
+    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
+    // this thread's cells: rows r0, r0 + 4, ...  On 4-row tiles (one cell per
+    // thread) its populations and cotangents are loaded before the staging, to
+    // be in flight with it; on taller tiles that costs more than it hides
+    // (1024^2: +11 %).  Lanes past the lattice load a valid duplicate and skip
+    // the cell.
+    const int r0 = threadIdx.x / BX, xc = min(x, a.nx - 1);
+    auto load_cell = [&](int r, double (&f)[Q], double (&mu)[Q]) {
+        const int y = min(y0 + r, a.ny - 1);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(xc, y, i, a.nxb)];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xs = xc + ex(i), ys = y + ey(i);
+            xs = xs < 0 ? a.nx - 1 : (xs >= a.nx ? 0 : xs);
+            ys = ys < 0 ? a.ny - 1 : (ys >= a.ny ? 0 : ys);
+            mu[i] = A.lam_next[i * n + (long)ys * a.nx + xs];
+        }
+    };
+    double f0[Q], mu0[Q];
+    if constexpr (TY == 4) load_cell(r0, f0, mu0);
+    const double* phi = static_cast<const double*>(a.phi_in);
     if constexpr (GY) {
-        const double* phi = static_cast<const double*>(a.phi_in);
         stage_lds_rc<TY * Bars::RW, Bars::RW, 8>(&s.row[0][0], [&](int r, int c) {
             return phi[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - Bars::J + c, a.nx), pitch)];
         });
+    } else if constexpr (TY == 4) {
+        using C = Cross<double, TY>;
+        stage_two<TY * C::RW, C::RW, C::CH * BX, BX>(
+            &s.row[0][0],
+            [&](int r, int c) { return phi[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - C::J + c, a.nx), pitch)]; },
+            &s.col[0][0],
+            [&](int r, int c) { return phi[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)]; });
     } else {
-        stage_cross<double, TY>(s, static_cast<const double*>(a.phi_in), x0, y0, a.nx, a.ny, pitch);
+        stage_cross<double, TY>(s, phi, x0, y0, a.nx, a.ny, pitch);
     }
     __syncthreads();
     constexpr int J = Bars::J;
-    const int lx = threadIdx.x & (BX - 1), x = x0 + lx;
-    for (int r = threadIdx.x / BX; r < TY; r += NT / BX) {
+    for (int r = r0; r < TY; r += NT / BX) {
         const int y = y0 + r;
         if (y >= a.ny) break;
         const double pc = s.row[r][J + lx];
@@ -267,21 +337,23 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
         if constexpr (GY) gy = A.rho[plane_at(y, x, pitch)];  // this cell's rho is stored there below
         const double Fx = FORCE == FORCE_ZC ? -gx : -2.0 * pc * gx;
         const double Fy = FORCE == FORCE_ZC ? -gy : -2.0 * pc * gy;
-        double f[Q];
+        double f[Q], mu[Q];
+        if (TY == 4 && r == r0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = a.f_in[fidx(x, y, i, a.nxb)];
+            for (int i = 0; i < Q; ++i) {
+                f[i] = f0[i];
+                mu[i] = mu0[i];
+            }
+        } else {
+            load_cell(r, f, mu);
+        }
         double rho, jx, jy;
         moments(f, rho, jx, jy);
         const double ir = 1.0 / rho, w = a.omega;
         const double mx = jx + Fx, my = jy + Fy;
-        double mu[Q];
         double rb = 0, jbx = 0, jby = 0, fbx = 0, fby = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int xs = x + ex(i), ys = y + ey(i);
-            xs = xs < 0 ? a.nx - 1 : (xs >= a.nx ? 0 : xs);
-            ys = ys < 0 ? a.ny - 1 : (ys >= a.ny ? 0 : ys);
-            mu[i] = A.lam_next[i * n + (long)ys * a.nx + xs];
             double ar, axx, ayy, br, bx, by;
             dA(i, ir, jx, jy, ar, axx, ayy);
             dA(i, ir, mx, my, br, bx, by);
@@ -321,13 +393,13 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
     const int x0 = blockIdx.x * BX, y0 = blockIdx.y * TY;
     const int pitch = a.nxb * BX;
     const long n = (long)a.nx * a.ny;
-    stage_lds_rc<TY * C::RW, C::RW, 8>(&rowx[0][0], [&](int r, int c) {
-        return A.ax[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - C::J + c, a.nx), pitch)];
-    });
-    if constexpr (!GY) {
-        stage_lds_rc<C::CH * BX, BX, 8>(&coly[0][0], [&](int r, int c) {
-            return A.ay[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)];
-        });
+    auto ax_at = [&](int r, int c) { return A.ax[plane_at(min(y0 + r, a.ny - 1), wrap_fast(x0 - C::J + c, a.nx), pitch)]; };
+    auto ay_at = [&](int r, int c) { return A.ay[plane_at(wrap_fast(y0 - C::J + r, a.ny), min(x0 + c, a.nx - 1), pitch)]; };
+    if constexpr (!GY && TY == 4) {
+        stage_two<TY * C::RW, C::RW, C::CH * BX, BX>(&rowx[0][0], ax_at, &coly[0][0], ay_at);
+    } else {
+        stage_lds_rc<TY * C::RW, C::RW, 8>(&rowx[0][0], ax_at);
+        if constexpr (!GY) stage_lds_rc<C::CH * BX, BX, 8>(&coly[0][0], ay_at);
     }
     __syncthreads();
     constexpr int J = C::J;
