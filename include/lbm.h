@@ -244,7 +244,9 @@ lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride
 
 /* ---- reverse mode ---------------------------------------------------------- */
 
-/* Device scratch needed by lbm_adjoint_step for this domain (bytes). */
+/* Device scratch needed by lbm_adjoint_step and lbm_adjoint_steps for this
+ * domain (bytes): four FP64 planes of the padded lattice, per-tile partials,
+ * and one FP64 plane of the lattice that only lbm_adjoint_steps uses. */
 lbm_status lbm_adjoint_workspace_bytes(const lbm_domain* d, size_t* bytes);
 
 /* One reverse-mode step (asynchronous), the transpose of the Jacobian of the
@@ -277,8 +279,8 @@ lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, i
  * that forbid allocation).  Same contract and result as lbm_adjoint_step; the
  * scratch of its kernels is a fixed device array inside the library, one per
  * GPU, of lbm_adjoint_noalloc_max_bytes() bytes (32 MiB: lattices up to about
- * 1000 x 1000; the library's adjoint scratch is 4 FP64 planes of the padded
- * lattice plus per-tile partials, lbm_adjoint_workspace_bytes).  LBM_EINVAL
+ * 1000 x 1000; one step's scratch is 4 FP64 planes of the padded lattice
+ * plus per-tile partials).  LBM_EINVAL
  * when the domain needs more.  Nothing is allocated and nothing needs
  * clearing (every scratch word is written before it is read in a call).  All
  * calls on one GPU share that GPU's array: calls that overlap on one GPU

@@ -1,5 +1,8 @@
 // Reverse-mode (adjoint) step of the HDM pseudopotential lattice Boltzmann
-// step, FP64, Shan-Chen or Zhang-Chen force.
+// step, FP64, Shan-Chen or Zhang-Chen force.  Every function here rounds each
+// product (no contracted multiply-adds; explicit fma() calls excepted), so
+// the instantiations of a kernel for different paths round alike and the
+// paths agree bitwise.
 //
 // With the equilibrium in momentum form A_i(rho, m) = w_i [rho + 3 e.m +
 // (4.5 (e.m)^2 - 1.5 |m|^2)/rho], one step is
@@ -39,6 +42,7 @@ struct AdjEos {
 };
 
 __device__ inline void eos_parts(int kind, double b, double rho, double& rep, double& drep, double& att, double& datt) {
+#pragma clang fp contract(off)
     if (kind == EOS_CS) {
         const double eta = 0.25 * b * rho, om = 1.0 - eta;
         const double N = 1.0 + eta * (1.0 + eta * (1.0 - eta));
@@ -69,6 +73,7 @@ __device__ inline void eos_parts(int kind, double b, double rho, double& rep, do
 }
 
 __device__ inline void dA(int i, double ir, double mx, double my, double& dr, double& dmx, double& dmy) {
+#pragma clang fp contract(off)
     const double em = double(ex(i)) * mx + double(ey(i)) * my;
     const double m2 = mx * mx + my * my;
     const double w = wq<double>(i);
@@ -81,12 +86,13 @@ __device__ inline void dA(int i, double ir, double mx, double my, double& dr, do
 // order; unrolled when the line keeps the full radius J (every long axis).
 template <int J, typename Op>
 __device__ inline double dline(const double* __restrict__ c, const double* base, int stride, int taps, Op op) {
+#pragma clang fp contract(off)
     double s = 0.0;
     if (taps == J) {
 #pragma unroll
-        for (int j = 1; j <= J; ++j) s += c[j - 1] * (op(base[j * stride]) - op(base[-j * stride]));
+        for (int j = 1; j <= J; ++j) s = fma(c[j - 1], op(base[j * stride]) - op(base[-j * stride]), s);
     } else {
-        for (int j = 1; j <= taps; ++j) s += c[j - 1] * (op(base[j * stride]) - op(base[-j * stride]));
+        for (int j = 1; j <= taps; ++j) s = fma(c[j - 1], op(base[j * stride]) - op(base[-j * stride]), s);
     }
     return s;
 }
@@ -100,6 +106,13 @@ struct AdjArgs {
     double* __restrict__ ubl;             // U_bar local part
     double* __restrict__ rho;
     double* __restrict__ partial;         // [blocks][2]
+    // Between the steps of one multi-step call the cotangent is kept as nine
+    // planes plus one scalar plane c, lam_i = lam_local_i + c (the density
+    // term, the same for all nine): the non-local pass writes c (add_out)
+    // instead of adding it to the nine planes, the next step's local pass
+    // adds it when it pulls lam_next (add_next).  Null: full planes.
+    const double* __restrict__ add_next;  // [ny][nx]
+    double* __restrict__ add_out;         // [ny][nx]
     int accumulate;                       // 1: add this step's partials to the stored ones
     AdjEos e;
 };
@@ -117,6 +130,7 @@ struct AdjArgs {
 //   MODE 1: U_bar_local plane += c D_y a_y, c = 1 (ZC) or -s / (2 Phi) (SC).
 template <int FORCE, int MODE>
 __global__ void __launch_bounds__(NT) k_adj_dy(AdjArgs A, int nchunk) {
+#pragma clang fp contract(off)
     constexpr int R = Radius<double>::value, TY = 8;
     constexpr int NB = (R - 3 + TY - 1) / TY;
     const StepArgs<double>& a = A.s;
@@ -231,6 +245,7 @@ __global__ void __launch_bounds__(NT) k_adj_dy(AdjArgs A, int nchunk) {
 // batches of 8 loads per thread took three memory round trips per tile.
 template <int NR, int WR, int NC, int WC, typename SrcR, typename SrcC>
 __device__ inline void stage_two(double* __restrict__ dr, SrcR sr, double* __restrict__ dc, SrcC sc) {
+#pragma clang fp contract(off)
     constexpr int PR = (NR + NT - 1) / NT, PC = (NC + NT - 1) / NT;
     const int tid = threadIdx.x;
     double vr[PR], vc[PC];
@@ -278,9 +293,12 @@ struct RowBar {
 
 // Pass 1: per 64 x TY tile, stage phi_t, recompute F and D Phi, pull lam_next,
 // local adjoint of collision and force.  GY: D_y of the potential operand is
-// read from the rho plane (k_adj_dy) and only the row bar is staged.
-template <int FORCE, int TY, bool GY = false>
+// read from the rho plane (k_adj_dy) and only the row bar is staged.  FIN:
+// lam_next is in factored form (AdjArgs::add_next); FOUT (pass 2): write the
+// density term to add_out instead of adding it to the nine planes.
+template <int FORCE, int TY, bool GY = false, bool FIN = false>
 __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
+#pragma clang fp contract(off)
     using Bars = typename std::conditional<GY, RowBar<TY>, Cross<double, TY>>::type;
     __shared__ Bars s;
     const StepArgs<double>& a = A.s;
@@ -304,6 +322,7 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
             xs = xs < 0 ? a.nx - 1 : (xs >= a.nx ? 0 : xs);
             ys = ys < 0 ? a.ny - 1 : (ys >= a.ny ? 0 : ys);
             mu[i] = A.lam_next[i * n + (long)ys * a.nx + xs];
+            if constexpr (FIN) mu[i] += A.add_next[(long)ys * a.nx + xs];
         }
     };
     double f0[Q], mu0[Q];
@@ -357,11 +376,11 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
             double ar, axx, ayy, br, bx, by;
             dA(i, ir, jx, jy, ar, axx, ayy);
             dA(i, ir, mx, my, br, bx, by);
-            rb += mu[i] * ((w - 1.0) * ar + br);
-            jbx += mu[i] * ((w - 1.0) * axx + bx);
-            jby += mu[i] * ((w - 1.0) * ayy + by);
-            fbx += mu[i] * bx;
-            fby += mu[i] * by;
+            rb = fma(mu[i], fma(w - 1.0, ar, br), rb);
+            jbx = fma(mu[i], fma(w - 1.0, axx, bx), jbx);
+            jby = fma(mu[i], fma(w - 1.0, ayy, by), jby);
+            fbx = fma(mu[i], bx, fbx);
+            fby = fma(mu[i], by, fby);
         }
         const long o = (long)y * a.nx + x;
 #pragma unroll
@@ -383,8 +402,9 @@ __global__ void __launch_bounds__(NT) k_adj_local(AdjArgs A) {
 
 // Pass 2: D applied to the a planes (staged like phi), U_bar, density term,
 // parameter partials per workgroup (fixed order).
-template <int FORCE, int TY, bool GY = false>
+template <int FORCE, int TY, bool GY = false, bool FOUT = false>
 __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
+#pragma clang fp contract(off)
     using C = Cross<double, TY>;
     __shared__ double rowx[TY][C::RW];                 // row bar of a_x
     __shared__ double coly[GY ? 1 : C::CH][BX];        // column bar of a_y (GY: unused)
@@ -435,10 +455,16 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
         const double dUdrho = A.e.g * (A.e.c_rep * drep - A.e.c_att * datt - 1.0 / 3.0);
         const double dUdg = A.e.c_rep * rep - A.e.c_att * att - rho / 3.0;
         const double dUdT = A.e.g * (A.e.kR * rep - A.e.c_attT * att);
-        const double add = ub * dUdrho;
+        // the density term is rounded before it is added (no fused multiply-add),
+        // so the factored and the full form of the cotangent agree bitwise
+        const double add = __dmul_rn(ub, dUdrho);
         const long o = (long)y * a.nx + x;
+        if constexpr (FOUT) {
+            A.add_out[o] = add;
+        } else {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) A.lam[k * n + o] += add;
+            for (int k = 0; k < Q; ++k) A.lam[k * n + o] += add;
+        }
         sg += ub * dUdg;
         sT += ub * dUdT;
     }
@@ -463,6 +489,7 @@ __global__ void __launch_bounds__(NT) k_adj_nonlocal(AdjArgs A) {
 // grad[0..1] += fixed-order sums of the pass-2 partials (one workgroup).
 static __global__ void __launch_bounds__(NT) k_adj_accumulate(const double* __restrict__ partial, long nblocks,
                                                        double* __restrict__ grad) {
+#pragma clang fp contract(off)
     __shared__ double red[2][NT / BX];
     double t0 = 0, t1 = 0;
     for (long b = threadIdx.x; b < nblocks; b += NT) { t0 += partial[2 * b]; t1 += partial[2 * b + 1]; }
@@ -483,6 +510,7 @@ static __global__ void __launch_bounds__(NT) k_adj_accumulate(const double* __re
 static __global__ void __launch_bounds__(NT) k_adj_rho0(const double* __restrict__ lam0,
                                                  const double* __restrict__ ux0, const double* __restrict__ uy0,
                                                  long n, double* __restrict__ out) {
+#pragma clang fp contract(off)
     for (long c = blockIdx.x * (long)NT + threadIdx.x; c < n; c += (long)gridDim.x * NT) {
         const double ux = ux0 ? ux0[c] : 0.0, uy = uy0 ? uy0[c] : 0.0;
         const double usq = ux * ux + uy * uy;

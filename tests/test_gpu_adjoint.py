@@ -193,15 +193,20 @@ def test_record_equals_stepping(variant, nx, ny):
 
 
 @pytest.mark.parametrize("force", ["sc", "zc"])
-def test_adjoint_steps_equal_single_steps(force):
+@pytest.mark.parametrize("nx,ny,variant", [(48, 40, 0), (96, 120, 3)])
+def test_adjoint_steps_equal_single_steps(force, nx, ny, variant):
     """lbm_adjoint_steps over a recorded segment: lam bitwise that of single
-    reverse steps, the parameter gradient equal to summation order."""
-    po, rho0, _, _ = case("pr", force, 48, 40)
+    reverse steps, the parameter gradient equal to summation order.  With
+    column marches (variant 3, ny > 79) the inner steps pass the cotangent
+    as nine planes plus the density-term plane; the sum they form is the one
+    the single steps store."""
+    po, rho0, _, _ = case("pr", force, nx, ny)
     n = 9
     d = L.Domain(lib_params(po), dev(rho0))
+    d.set_kernel(variant, 0)
     st = d.new_states(n + 1)
     d.record(st, n)
-    lam0 = dev(np.random.default_rng(7).standard_normal((9, 40, 48)))
+    lam0 = dev(np.random.default_rng(7).standard_normal((9, ny, nx)))
     ws = d.adjoint_workspace()
     lam_a, tmp = lam0.clone(), torch.empty_like(lam0)
     grad_a = torch.zeros(2, dtype=torch.float64, device="cuda")
