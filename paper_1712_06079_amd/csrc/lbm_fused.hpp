@@ -50,8 +50,8 @@ struct FusedShape {
 // window: output k sits at window position R + k; every window value is loaded
 // once from LDS and added to the K outputs with the coefficients c(m - R - k),
 // which are K consecutive entries of the sign-folded table (one scalar load).
-template <int FORCE, int K, int R>
-__device__ inline void stencil_window(const double* __restrict__ base, int stride, const double* __restrict__ tab,
+template <int FORCE, int K, int R, typename BT = double>
+__device__ inline void stencil_window(const BT* __restrict__ base, int stride, const double* __restrict__ tab,
                                       double (&acc)[K], double (&accu)[K]) {
     static_assert(R + K - 1 <= TAB_OFF && K <= KT, "stencil window outside the coefficient table");
 #pragma unroll
