@@ -867,13 +867,17 @@ def long_run_comparison(steps: int):
     return out
 
 
-def size_curve(sizes, steps: int):
-    """MLUPS of the large dynamic recipe at other lattice sizes (FP64 and FP32)."""
+def size_curve(sizes, steps: int, warm_s: float = 1.0):
+    """MLUPS of the large dynamic recipe at other lattice sizes (FP64 and FP32),
+    each after `warm_s` seconds of the same step on the same domain (see
+    device_warmup: 200 steps of 2048^2 would otherwise fall inside the
+    device's transient)."""
+    import torch
     out = []
     for n in sizes:
         for prec in ("f64", "f32"):
             d, p, _ = _domain(f"c5_{n}", prec)
-            d.step(10)
+            device_warmup(d, warm_s, torch.cuda.current_stream())
             ms = _timed_steps(d, steps, f"curve {n} {prec}", chunk=steps)
             mlups = n * n * steps / (ms * 1e-3) / 1e6
             es = 8 if prec == "f64" else 4
