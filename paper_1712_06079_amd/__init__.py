@@ -237,7 +237,10 @@ class Domain:
         return self._h
 
     def set_kernel(self, variant: int = 0, tile_y: int = 0):
-        """0 automatic, 1 two-pass reference, 2 fused tiles, 3 fused strip march."""
+        """0 automatic, 1 two-pass reference, 2 fused tiles, 3 fused strip march.
+        The variant also picks how the reverse step takes its y derivatives
+        on a long y axis: column marches under 3, tiles under 1 and 2, and
+        by lattice size under 0 (see lbm_set_kernel in include/lbm.h)."""
         check(library().lbm_set_kernel(self._h, variant, tile_y))
 
     def set_chunks(self, nchunk: int = 0):
