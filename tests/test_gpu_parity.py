@@ -398,6 +398,23 @@ def test_largest_lattice_properties(prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(1 << 21, 5), (5, 1 << 21)])
+def test_longest_sides_match_oracle(nx, ny, prec):
+    """The longest lattice sides the library accepts (2^21): a noisy slab
+    across the long axis, 3 steps, every density against the oracle.  The
+    kernels' index arithmetic (periodic wrap by the FP32 reciprocal, 24-bit
+    plane offsets) is exact up to these sides."""
+    po = PINS.c1_params(nx=nx, ny=ny)
+    rv, rl, _ = O.maxwell(po, po.T)
+    axis = "x" if nx > ny else "y"
+    rho0 = I.slab(nx, ny, rv, rl, 5.0, axis=axis, noise=1e-4 * rv, seed=31)
+    got = gpu_run(po, rho0, 3, prec)["rho"]
+    ref = oracle_run(po, rho0, 3)["rho"]
+    assert rel_err(got, ref) < TOL[prec], rel_err(got, ref)
+    torch.cuda.empty_cache()
+
+
 def test_sigma_from_gpu_slab():
     """Sec. 5.3's integration method on a simulated flat interface: the GPU
     supplies the slab (van der Waals, T_r = 0.7, 8 x 128, 3000 steps), the
