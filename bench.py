@@ -444,40 +444,37 @@ def surface_tension_report(slab_steps: int = 40000, drop_steps: int = 20000):
 
 
 def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.0, t_star_end: float = 1.5,
-                  every: int = 50):
-    """Sec. 5.5: a droplet splashing on a thin liquid film.  1000 x 300, PR water
-    (a = 9/49, b = 2/21, omega = 0.344, k = 0.04) at T_r = 0.6, SC + HDM,
-    no-slip walls in y (halfway bounce-back, mirror closure of Eq. 20),
-    periodic x; film of height 30 (a tenth of the height) on the lower wall;
-    interfaces tanh with W = 4.  The paper's droplet (R = 50, U = 0.108) goes
-    non-finite within 300-550 steps here at every tau tried (0.69 .. 1.5;
-    U <= 0.05 at tau 0.824 is stable), so the Reynolds numbers Re = U D / nu_l
-    are reached with U = 0.05 and D = 216 (R = 108) at the paper's tau for each
-    Re (tau = 3 U D / Re + 1/2: 1.31, 0.824, 0.687).  The droplet starts merged
-    with the film by 3 lattice units (centre at y = 30 + R - 3), moving down at
-    U (initial velocity -U weighted by its liquid fraction).  The spread radius
-    r(t) is half the width of the liquid run through x = 500 in the row just
-    above the initial film surface (y = 31); C of r/D = C sqrt(U (t - t0)/D) is
+                  every: int = 50, tau_floor: float = 0.824):
+    """Sec. 5.5: a droplet splashing on a thin liquid film.  PR water (a = 9/49,
+    b = 2/21, omega = 0.344, k = 0.04) at T_r = 0.6, SC + HDM, no-slip walls
+    in y (halfway bounce-back, mirror closure of Eq. 20), periodic x; film of
+    height 30 on the lower wall; interfaces tanh with W = 4.  The paper's
+    droplet (R = 50, U = 0.108 on 1000 x 300) goes non-finite within 300-550
+    steps here at every tau tried (0.69 .. 1.5; U <= 0.05 at tau 0.824 is
+    stable), so the Reynolds numbers Re = U D / nu_l are reached with U = 0.05:
+    D = 216 (R = 108) on 1000 x 300 at the tau each Re then needs
+    (tau = 3 U D / Re + 1/2: 1.31 for Re = 40, 0.824 for 100); where that tau
+    falls below `tau_floor` (Re = 173: 0.687, non-finite after 300 steps) the
+    run keeps tau = tau_floor and grows the droplet instead,
+    D = Re (tau - 1/2) / (3 U) (Re = 173: D = 374 on 1600 x 520, the lattice
+    scaled with D).  The droplet starts merged with the film by 3
+    lattice units (centre at y = 30 + R - 3), moving down at U (initial
+    velocity -U weighted by its liquid fraction).  The spread radius r(t) is
+    half the width of the liquid run through x = nx / 2 in the row just above
+    the initial film surface (y = 31); C of r/D = C sqrt(U (t - t0)/D) is
     fitted (with the contact time t0) on t* = U t / D in [0.2, 1.2].
     We = rho_l U^2 D / sigma, sigma from Laplace's law (droplet R = 32 on a
     periodic 128^2 lattice, 20 000 steps)."""
     import torch
 
     import paper_1712_06079_amd as L
-    nx, ny, hf = 1000, 300, 30.0
-    D = 2 * R
+    hf = 30.0
     base = dict(eos="pr", force="sc", a=9 / 49, b=2 / 21, R=1.0, omega=0.344, k=0.04)
-    p0 = L.Params(nx=nx, ny=ny, walls=1, tau=1.0, **base)
+    p0 = L.Params(nx=1000, ny=300, walls=1, tau=1.0, **base)
     tc, _ = L.critical(p0)
     T = 0.6 * tc
     rv, rl, _ = L.maxwell(p0, T)
-    y, x = np.mgrid[0:ny, 0:nx].astype(float)
-    film = 0.5 * (1 - np.tanh(2 * (y - hf) / 4.0))
-    cy = hf + R - 3.0
-    drop = 0.5 * (1 - np.tanh(2 * (np.hypot(x - nx / 2, y - cy) - R) / 4.0))
-    rho0 = rv + (rl - rv) * np.maximum(film, drop)
-    uy0 = -U * drop * (drop > film)
-    out = {"lattice": [nx, ny], "T_r": 0.6, "U": U, "D": D, "film": hf, "rho_l": rl, "rho_v": rv, "runs": [],
+    out = {"T_r": 0.6, "U": U, "film": hf, "rho_l": rl, "rho_v": rv, "tau_floor": tau_floor, "runs": [],
            "paper": {"U": 0.108, "D": 100, "We": 117, "C": 1.3}}
     pl = L.Params(nx=128, ny=128, tau=1.0, T=T, **base)
     dl = L.Domain(pl, torch.from_numpy(I.droplet(128, 128, rv, rl, 32.0, 4.0)).cuda())
@@ -487,11 +484,24 @@ def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.
     re_ = float(np.sqrt(((rho - rho[0, 0]) / (rho[64, 64] - rho[0, 0])).sum() / np.pi))
     sigma = float((pr[64, 64] - pr[0, 0]) * re_)
     out["sigma_L"] = sigma
-    out["We"] = rl * U * U * D / sigma if sigma > 0 else None
     del dl
-    steps = int(t_star_end * D / U) // every * every
     for Re in re_list:
+        D = 2 * R
         tau = 3 * U * D / Re + 0.5
+        nx, ny = 1000, 300
+        if tau < tau_floor:  # a larger droplet at a stable tau, the lattice scaled with it
+            tau = tau_floor
+            D = Re * (tau - 0.5) / (3 * U)
+            nx = max(1000, int(round(4.3 * D / 64)) * 64)
+            ny = max(300, int(np.ceil((hf + 1.31 * D) / 8)) * 8)
+        Rd = D / 2
+        y, x = np.mgrid[0:ny, 0:nx].astype(float)
+        film = 0.5 * (1 - np.tanh(2 * (y - hf) / 4.0))
+        cy = hf + Rd - 3.0
+        drop = 0.5 * (1 - np.tanh(2 * (np.hypot(x - nx / 2, y - cy) - Rd) / 4.0))
+        rho0 = rv + (rl - rv) * np.maximum(film, drop)
+        uy0 = -U * drop * (drop > film)
+        steps = int(t_star_end * D / U) // every * every
         p = L.Params(nx=nx, ny=ny, walls=1, tau=tau, T=T, **base)
         d = L.Domain(p, torch.from_numpy(rho0).cuda(), None, torch.from_numpy(uy0).cuda())
         ts, rs = [], []
@@ -518,7 +528,9 @@ def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.
                     hi += 1
                 ts.append(done)
                 rs.append(0.5 * (hi - lo + 1))
-        run = {"Re": Re, "tau": tau, "steps": done, "finite": finite, "mlups": round(nx * ny * done / (ms * 1e-3) / 1e6, 1),
+        run = {"Re": Re, "tau": round(tau, 4), "D": round(D, 1), "lattice": [nx, ny], "steps": done, "finite": finite,
+               "We": round(rl * U * U * D / sigma, 1) if sigma > 0 else None,
+               "mlups": round(nx * ny * done / (ms * 1e-3) / 1e6, 1),
                "t_star": [round(U * t / D, 4) for t in ts], "r_over_D": [round(r / D, 4) for r in rs]}
         ts_a, rs_a = np.array(ts, float), np.array(rs, float)
         sel = (U * ts_a / D >= 0.2) & (U * ts_a / D <= 1.2)
@@ -528,7 +540,8 @@ def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.
                 run["C"] = round(float(np.sqrt(slope / (D * U))), 4)
                 run["t0"] = round(float(-icpt / slope), 1)
         out["runs"].append(run)
-        print(f"[bench] splash Re {Re}: finite {finite}, C {run.get('C')}, We {out['We']:.1f}", file=sys.stderr, flush=True)
+        print(f"[bench] splash Re {Re}: D {D:.0f} on {nx}x{ny}, tau {tau:.3f}, finite {finite}, C {run.get('C')}, "
+              f"We {run['We']}", file=sys.stderr, flush=True)
         del d
     return out
 
