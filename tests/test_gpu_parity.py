@@ -415,6 +415,51 @@ def test_longest_sides_match_oracle(nx, ny, prec):
     torch.cuda.empty_cache()
 
 
+def _random_cases(n=24, seed=20261203):
+    """Seeded draws of shape, EOS, force, gradient, precision, walls and step
+    kernel (only the combinations the library supports)."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    while len(cases) < n:
+        nx, ny = int(rng.integers(5, 300)), int(rng.integers(5, 300))
+        eos = str(rng.choice(["vdw", "pr", "cs", "rk", "rks"]))
+        force = str(rng.choice(["sc", "zc", "hybrid"]))
+        grad = str(rng.choice(["hdm", "cdm", "cdm9"]))
+        prec = str(rng.choice(["f64", "f32"]))
+        walls = int(rng.random() < 0.3)
+        if walls and grad == "cdm9":
+            continue
+        variants = [0, 2] + ([] if walls else [1])
+        R = 39 if prec == "f64" else 28
+        nb = (R - 3 + 7) // 8
+        if grad == "hdm" and not walls and ny > 2 * R + 1 and ny > (nb + 2) * 8 + 3:
+            variants.append(3)
+        cases.append((nx, ny, eos, force, grad, prec, walls, int(rng.choice(variants))))
+    return cases
+
+
+@pytest.mark.parametrize("nx,ny,eos,force,grad,prec,walls,variant", _random_cases())
+def test_random_configurations_match_oracle(nx, ny, eos, force, grad, prec, walls, variant):
+    """24 seeded configurations drawn across every option at once (droplet
+    with velocity noise at T_r = 0.85, 20 steps), densities against the
+    oracle: combinations the structured tests do not pair."""
+    po = PINS.eos_params(eos)
+    po.nx, po.ny, po.force, po.grad, po.walls = nx, ny, force, grad, walls
+    po.A = 0.3 if force == "hybrid" else 0.0
+    tc, _ = O.critical(po)
+    po.T = 0.85 * tc
+    rv, rl, _ = O.maxwell(po, po.T)
+    seed = nx * 1000 + ny
+    rho0 = I.droplet(nx, ny, rv, rl, max(2.0, min(nx, ny) / 4.0), 4.0, cx=nx * 0.45, cy=ny * 0.55,
+                     noise=1e-3 * rv, seed=seed)
+    ux0 = I.uniform_noise((ny, nx), 1e-3, seed + 1)
+    uy0 = I.uniform_noise((ny, nx), 1e-3, seed + 2)
+    ref = oracle_run(po, rho0, 20, ux0, uy0)
+    got = gpu_run(po, rho0, 20, prec, ux0, uy0, variant=variant)
+    assert np.all(np.isfinite(ref["rho"]))
+    assert rel_err(got["rho"], ref["rho"]) < TOL[prec], rel_err(got["rho"], ref["rho"])
+
+
 def test_sigma_from_gpu_slab():
     """Sec. 5.3's integration method on a simulated flat interface: the GPU
     supplies the slab (van der Waals, T_r = 0.7, 8 x 128, 3000 steps), the
