@@ -118,6 +118,43 @@ def test_rollout_gradient_finite_differences():
     assert abs(ad_r / fd_r - 1) < 1e-5, (ad_r, fd_r)
 
 
+def _random_adjoint_cases(n=12, seed=1712):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for _ in range(n):
+        nx, ny = int(rng.integers(5, 260)), int(rng.integers(5, 260))
+        eos = str(rng.choice(["vdw", "pr", "cs", "rk", "rks"]))
+        force = str(rng.choice(["sc", "zc"]))
+        grad = str(rng.choice(["hdm", "cdm"]))
+        variants = [0, 2] + ([3] if grad == "hdm" and ny > 79 else [])
+        cases.append((nx, ny, eos, force, grad, int(rng.choice(variants))))
+    return cases
+
+
+@pytest.mark.parametrize("nx,ny,eos,force,grad,variant", _random_adjoint_cases())
+def test_random_reverse_steps_match_oracle(nx, ny, eos, force, grad, variant):
+    """12 seeded configurations drawn across shape, EOS, force, gradient and
+    reverse-step path: one reverse step against the oracle's."""
+    po, rho0, _, _ = case(eos, force, nx, ny, seed=nx + ny)
+    po.grad = grad
+    f_t = O.run(po, O.init(po, rho0), 3)
+    lam_next = np.random.default_rng(nx * 1000 + ny).standard_normal(f_t.shape)
+    ref_lam, ref_grad = O.adjoint_step(po, f_t, lam_next)
+    d = L.Domain(lib_params(po), dev(rho0))
+    d.set_kernel(variant, 0)
+    d.set_populations(dev(f_t))
+    st = d.new_states(1)
+    d.save_state(st[0])
+    lam = torch.empty((9, ny, nx), dtype=torch.float64, device="cuda")
+    grad_t = torch.zeros(2, dtype=torch.float64, device="cuda")
+    d.adjoint_step(st[0], dev(lam_next), lam, grad_t, d.adjoint_workspace())
+    got = lam.cpu().numpy()
+    scale = np.abs(ref_lam).max()
+    assert np.max(np.abs(got - ref_lam)) < 1e-11 * scale, np.max(np.abs(got - ref_lam)) / scale
+    g = grad_t.cpu().numpy()
+    assert np.all(np.abs(g - ref_grad) < 1e-10 * np.maximum(1.0, np.abs(ref_grad))), (g, ref_grad)
+
+
 def test_column_march_and_tiles_agree_at_full_width():
     """A 2048 x 1024 reverse step with the y derivatives by column marches
     (the automatic choice on this lattice) and by tiles, both against the
