@@ -198,6 +198,31 @@ def test_batch_with_walls():
         assert np.max(np.abs(got - ref) / ref) < 1e-12, i
 
 
+@pytest.mark.parametrize("seed", [3, 4, 5, 6])
+def test_random_batches_equal_single_domains(seed):
+    """Seeded batches: 3-8 domains of random width (5-299) and height (5-79:
+    the explicit form along y, where the tiling cannot change a cell's
+    arithmetic), PR and CS, random walls, precision, Eq. 15 or not and
+    schedule; every domain bitwise the same domain stepped alone."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 9))
+    prec = str(rng.choice(["f64", "f32"]))
+    grad9 = bool(rng.random() < 0.25)
+    shapes = ([int(rng.integers(5, 300)) for _ in range(n)], [int(rng.integers(5, 80)) for _ in range(n)])
+    ps, rhos = sweep_params(n, seed, prec, shapes)
+    for p in ps:
+        p.grad = "cdm9" if grad9 else "hdm"
+        p.walls = 0 if grad9 else int(rng.random() < 0.4)
+    b = L.Batch(ps, [dev(r) for r in rhos])
+    sched = (int(rng.choice([4, 8])), int(rng.integers(0, 4)), int(rng.choice([0, 64, 512])))
+    b.set_schedule(*sched)
+    b.step(25)
+    for i, (p, r) in enumerate(zip(ps, rhos)):
+        d = L.Domain(p, dev(r))
+        d.step(25)
+        assert np.array_equal(b.domain(i).populations().cpu().numpy(), d.populations().cpu().numpy()), (i, sched)
+
+
 def test_batch_rejects_mixed_eq15():
     ps, rhos = sweep_params(4, 19, "f64", ([128, 64, 64, 128], [8, 8, 16, 8]))
     ps[2].grad = "cdm9"
