@@ -353,7 +353,7 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* tile_y, int32_t* 
  * (synchronises `stream`).  report (nullable) receives a JSON object of the
  * per-step times in ms, "cached": false and the choice.  The choice is kept
  * for the rest of the process under a key of the device architecture, the
- * batch's precision, force, gradient and domain shapes in order; a later call
+ * batch's precision, force and domains in order (shape, gradient, walls); a later call
  * for a batch with the same key applies it without timing (report
  * {"cached": true, "best": ...}). */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t stream, char* report, size_t report_len);

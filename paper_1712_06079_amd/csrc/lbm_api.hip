@@ -626,6 +626,8 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     const int ty = adj_ty(d);
     dim3 grid(d->nxb, (d->p.ny + ty - 1) / ty);
     const int nchunk = adj_dy_chunks(d);
+    if (nchunk == 0 && (add_next || add_out))  // only the column-march passes take the factored form
+        return fail(LBM_EINVAL, "factored cotangent without the column-march reverse step");
     const dim3 gdy((d->nxb + lbm::NT / lbm::BX - 1) / (lbm::NT / lbm::BX), nchunk > 0 ? nchunk : 1);
     auto launch = [&](auto force, auto tyc) {
         constexpr int F = decltype(force)::value, TY = decltype(tyc)::value;
@@ -714,8 +716,7 @@ lbm_status lbm_adjoint_steps(lbm_domain* d, const void* states, size_t stride, i
     // the last writes full planes.  On small lattices the nine extra gathers
     // of the scalar plane cost more latency than the 17 words save
     // (1024^2: 0.131 -> 0.160 ms; 4096^2: 1.84 -> 1.61 ms).
-    double* addp = adj_dy_chunks(d) > 0 ? reinterpret_cast<double*>(w + adj_layout(d).single) : nullptr;  // (the kernels
-    // take the factored form only with the column marches)
+    double* addp = adj_dy_chunks(d) > 0 ? reinterpret_cast<double*>(w + adj_layout(d).single) : nullptr;
     for (int64_t t = nsteps - 1; t >= 0; --t) {
         st = adjoint_kernels(d, base + (size_t)t * stride, cur, nxt, w, t == nsteps - 1 ? 0 : 1, stream,
                              t == nsteps - 1 ? nullptr : addp, t == 0 ? nullptr : addp);

@@ -193,8 +193,9 @@ lbm_status ensure_graph(lbm_batch* b) {
 }
 
 // Autotuner results of this process, keyed by what the timing depends on:
-// the device's architecture, the batch's precision, force and gradient, and
-// its domain shapes in order (the tile list is built from them).
+// the device's architecture, the batch's precision, force and use of Eq. 15,
+// and its domains in order: shape, gradient, walls (the tile list and the
+// per-tile work are built from them).
 struct TuneChoice {
     int tile_y, order, grid;
 };
@@ -210,7 +211,7 @@ lbm_status tune_key(const lbm_batch* b, std::string* key) {
     snprintf(buf, sizeof(buf), "%s|p%d|f%d|g%d|n%d|", prop.gcnArchName, b->prec, b->force, b->grad9, b->n);
     *key = buf;
     for (const auto* d : b->doms) {
-        snprintf(buf, sizeof(buf), "%dx%d%s,", d->p.nx, d->p.ny, d->p.walls ? "w" : "");
+        snprintf(buf, sizeof(buf), "%dx%dg%d%s,", d->p.nx, d->p.ny, d->p.grad, d->p.walls ? "w" : "");
         *key += buf;
     }
     return LBM_OK;
@@ -413,23 +414,29 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t probe_steps, hipStream_t str
     std::string key;
     lbm_status kst = tune_key(b, &key);
     if (kst != LBM_OK) return kst;
+    bool cached = false;
+    TuneChoice kept{};
     {
         std::lock_guard<std::mutex> lock(tune_mutex);
         auto it = tune_cache.find(key);
         if (it != tune_cache.end()) {
-            b->tile_y = it->second.tile_y;
-            b->order = it->second.order;
-            b->grid = it->second.grid;
-            lbm_status st = upload_tiles(b, stream);
-            if (st != LBM_OK) return st;
-            if (report && report_len) {
-                char buf[128];
-                snprintf(buf, sizeof(buf), "{\"cached\": true, \"best\": \"ty%d_o%d_g%d\"}", b->tile_y, b->order, b->grid);
-                std::strncpy(report, buf, report_len - 1);
-                report[report_len - 1] = 0;
-            }
-            return LBM_OK;
+            cached = true;
+            kept = it->second;
         }
+    }
+    if (cached) {  // (the lock is released: the upload synchronises the stream)
+        b->tile_y = kept.tile_y;
+        b->order = kept.order;
+        b->grid = kept.grid;
+        lbm_status st = upload_tiles(b, stream);
+        if (st != LBM_OK) return st;
+        if (report && report_len) {
+            char buf[128];
+            snprintf(buf, sizeof(buf), "{\"cached\": true, \"best\": \"ty%d_o%d_g%d\"}", b->tile_y, b->order, b->grid);
+            std::strncpy(report, buf, report_len - 1);
+            report[report_len - 1] = 0;
+        }
+        return LBM_OK;
     }
     // snapshot every domain's current populations
     const int cur0 = b->cur;
