@@ -211,9 +211,19 @@ int64_t lbm_step_count(const lbm_domain* d);
 lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
 
 /* Number of y chunks each 64-column strip is split into by the marching
- * kernel (host; for tuning and tests): 0 = automatic (one full set of resident
- * workgroups), otherwise min(nchunk, ny).  LBM_EINVAL for nchunk < 0. */
+ * kernel (host; for tuning and tests): 0 = automatic (the most chunks whose
+ * workgroups are all resident at once), otherwise min(nchunk, ny).
+ * LBM_EINVAL for nchunk < 0. */
 lbm_status lbm_set_chunks(lbm_domain* d, int32_t nchunk);
+
+/* How the marching kernel reads and writes the populations and writes the
+ * next potential field, each touched once per step (host; results are the
+ * same bitwise in every mode): 0 = automatic (plain, cached accesses when the
+ * domain's state, both population and potential buffers, fits in the 256 MiB
+ * last-level cache of gfx950 so that the next step reads it from there,
+ * otherwise non-temporal), 1 = non-temporal, 2 = plain.  Odd N_x always uses
+ * non-temporal accesses.  LBM_EINVAL for other values. */
+lbm_status lbm_set_access(lbm_domain* d, int32_t access);
 
 /* Check the current density (Eq. 3) for non-finite values (synchronises
  * `stream`): *ok = 1 if every rho is finite, else 0 (and the call returns

@@ -24,6 +24,7 @@ struct lbm_domain {
     int variant;       // 0 fused (automatic), 1 two-pass reference, 2 fused tiles, 3 fused march
     int tile_y;        // rows per tile or marching block (0 = default)
     int chunks;        // y chunks per strip of the marching kernel (0 = automatic)
+    int access;        // marching kernel's population accesses: 0 automatic, 1 non-temporal, 2 plain
     int ncu;           // compute units of the device
     int march_occ[2];  // resident marching workgroups per CU (block rows 4, 8; 0 = not queried)
     char* ws;

@@ -100,13 +100,30 @@ struct MarchShape {
     static_assert(SEG % 2 == 0, "each lane of a pair finishes half a segment");
 };
 
+// Population loads and stores and the stores of phi_{t+1}: each value is
+// touched once per step.  Where the step's state (both population and
+// potential buffers) exceeds the last-level cache, non-temporal accesses
+// (NTA) keep it from evicting the potential rows, which are read again a few
+// blocks later.  Where the whole state stays resident in that cache from one
+// step to the next, plain accesses let the next step read it from there.
+template <bool NTA, typename T>
+__device__ inline T ld_once(const T* p) {
+    if constexpr (NTA) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NTA, typename T>
+__device__ inline void st_once(T v, T* p) {
+    if constexpr (NTA) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Interior cells are handled in pairs (x, x+1), x even, one pair per lane, so
 // that a lane moves both cells' populations with one 16-byte (FP64) or 8-byte
 // (FP32) access.  VEC selects those paired accesses; it requires an even N_x
 // (a pair never straddles the periodic seam).  Odd N_x uses per-cell accesses.
 // The register budget follows MarchShape::WAVES (VGPRs + AGPRs <= 512 / WAVES);
 // it is a hard limit, not a hint.
-template <typename Real, int FORCE, int TY, bool VEC>
+template <typename Real, int FORCE, int TY, bool VEC, bool NTA>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchShape<Real, FORCE, TY, Radius<Real>::value>::WAVES))) k_march(StepArgs<Real> a, int nchunk) {
     constexpr int R = Radius<Real>::value;
     using M = MarchShape<Real, FORCE, TY, R>;
@@ -211,9 +228,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
 #pragma unroll
         for (int j = 0; j < TY; ++j) pfar[j] = (double)phin[(long)wrapy(yn + 4 + NB * TY + j) * pitch + xcol];
     };
-    // The interior populations and the new state are touched once per step:
-    // non-temporal accesses keep them from evicting the potential rows, which
-    // are read again a few blocks later.
     auto issue_f = [&](int yn) {      // interior populations of block yn (after their last use)
 #pragma unroll
         for (int i = 0; i < M::NP; ++i) {
@@ -223,7 +237,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
             if (VEC) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(a.f_in + fidx(xa, yw, q, nxb)));
+                    const V2 v = ld_once<NTA>(reinterpret_cast<const V2*>(a.f_in + fidx(xa, yw, q, nxb)));
                     fc[i][0][q] = v.x;
                     fc[i][1][q] = v.y;
                 }
@@ -231,8 +245,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                 const int xb = xpair[i][1];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    fc[i][0][q] = __builtin_nontemporal_load(a.f_in + fidx(xa, yw, q, nxb));
-                    fc[i][1][q] = __builtin_nontemporal_load(a.f_in + fidx(xb, yw, q, nxb));
+                    fc[i][0][q] = ld_once<NTA>(a.f_in + fidx(xa, yw, q, nxb));
+                    fc[i][1][q] = ld_once<NTA>(a.f_in + fidx(xb, yw, q, nxb));
                 }
             }
         }
@@ -619,10 +633,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                         V2 v;
                         v.x = v0;
                         v.y = v1;
-                        __builtin_nontemporal_store(v, reinterpret_cast<V2*>(a.f_out + fidx(x, y, q, nxb)));
+                        st_once<NTA>(v, reinterpret_cast<V2*>(a.f_out + fidx(x, y, q, nxb)));
                     } else {
-                        __builtin_nontemporal_store(v0, a.f_out + fidx(x, y, q, nxb));
-                        if (x + 1 < nx) __builtin_nontemporal_store(v1, a.f_out + fidx(x + 1, y, q, nxb));
+                        st_once<NTA>(v0, a.f_out + fidx(x, y, q, nxb));
+                        if (x + 1 < nx) st_once<NTA>(v1, a.f_out + fidx(x + 1, y, q, nxb));
                     }
                 }
                 double ph[2];
@@ -637,10 +651,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MarchSh
                     P __attribute__((ext_vector_type(2))) pv;
                     pv.x = (P)ph[0];
                     pv.y = (P)ph[1];
-                    __builtin_nontemporal_store(pv, reinterpret_cast<P __attribute__((ext_vector_type(2)))*>(pd));
+                    st_once<NTA>(pv, reinterpret_cast<P __attribute__((ext_vector_type(2)))*>(pd));
                 } else {
-                    __builtin_nontemporal_store((P)ph[0], pd);
-                    if (x + 1 < nx) __builtin_nontemporal_store((P)ph[1], pd + 1);
+                    st_once<NTA>((P)ph[0], pd);
+                    if (x + 1 < nx) st_once<NTA>((P)ph[1], pd + 1);
                 }
             }
         }
@@ -661,21 +675,24 @@ inline bool march_fits(int ny, int ty) {
 }
 
 // Launch over nchunk y chunks of every 64-column strip (nchunk in [1, ny]);
-// paired 16/8-byte population accesses when N_x is even.
+// paired 16/8-byte population accesses when N_x is even, plain (cached)
+// population accesses when `cached` and N_x is even, else non-temporal.
 template <typename Real, int FORCE, int TY>
-inline void launch_march_t(const StepArgs<Real>& a, int nchunk, hipStream_t s) {
+inline void launch_march_t(const StepArgs<Real>& a, int nchunk, bool cached, hipStream_t s) {
     const dim3 grid((unsigned)(a.nxb * nchunk));
-    if (a.nx % 2 == 0)
-        hipLaunchKernelGGL((k_march<Real, FORCE, TY, true>), grid, dim3(NT), 0, s, a, nchunk);
+    if (a.nx % 2 != 0)
+        hipLaunchKernelGGL((k_march<Real, FORCE, TY, false, true>), grid, dim3(NT), 0, s, a, nchunk);
+    else if (cached)
+        hipLaunchKernelGGL((k_march<Real, FORCE, TY, true, false>), grid, dim3(NT), 0, s, a, nchunk);
     else
-        hipLaunchKernelGGL((k_march<Real, FORCE, TY, false>), grid, dim3(NT), 0, s, a, nchunk);
+        hipLaunchKernelGGL((k_march<Real, FORCE, TY, true, true>), grid, dim3(NT), 0, s, a, nchunk);
 }
 
 template <typename Real, int FORCE>
-inline bool launch_march(const StepArgs<Real>& a, int ty, int nchunk, hipStream_t s) {
+inline bool launch_march(const StepArgs<Real>& a, int ty, int nchunk, bool cached, hipStream_t s) {
     switch (ty) {
-        case 4: launch_march_t<Real, FORCE, 4>(a, nchunk, s); return true;
-        case 8: launch_march_t<Real, FORCE, 8>(a, nchunk, s); return true;
+        case 4: launch_march_t<Real, FORCE, 4>(a, nchunk, cached, s); return true;
+        case 8: launch_march_t<Real, FORCE, 8>(a, nchunk, cached, s); return true;
         default: return false;
     }
 }

@@ -32,10 +32,11 @@ def dev(a):
     return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def gpu_run(po, rho0, steps, prec="f64", ux0=None, uy0=None, variant=0, tile=0, chunks=0):
+def gpu_run(po, rho0, steps, prec="f64", ux0=None, uy0=None, variant=0, tile=0, chunks=0, access=0):
     d = L.Domain(lib_params(po, prec), dev(rho0), dev(ux0), dev(uy0))
     d.set_kernel(variant, tile)
     d.set_chunks(chunks)
+    d.set_access(access)
     d.step(steps)
     m = d.moments()
     f = d.populations()
@@ -149,6 +150,23 @@ def test_march_matches_oracle(nx, ny, ty, chunks, prec):
     got = gpu_run(po, rho0, 40, prec, ux0, uy0, variant=3, tile=ty, chunks=chunks)
     assert rel_err(got["rho"], ref["rho"]) < TOL[prec]
     assert np.max(np.abs(got["f"] - ref["f"])) < TOL[prec] * np.max(np.abs(ref["f"]))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("force,nx,ny,ty", [("sc", 96, 150, 8), ("zc", 130, 100, 4), ("hybrid", 140, 88, 8),
+                                            ("sc", 33, 130, 8)])
+def test_march_access_modes(force, nx, ny, ty, prec):
+    """Plain and non-temporal population accesses of the marching kernel (the
+    automatic mode takes plain ones wherever the state fits in the last-level
+    cache, as on every lattice here; odd N_x always takes non-temporal ones)
+    give the same state bitwise, at the oracle's values."""
+    po, rho0, ux0, uy0 = variant_case("cs", force, nx, ny, seed=nx + ny + ty)
+    ref = oracle_run(po, rho0, 30, ux0, uy0)
+    runs = [gpu_run(po, rho0, 30, prec, ux0, uy0, variant=3, tile=ty, chunks=2, access=m) for m in (0, 1, 2)]
+    for r in runs[1:]:
+        assert np.array_equal(r["f"], runs[0]["f"])
+    assert rel_err(runs[0]["rho"], ref["rho"]) < TOL[prec]
+    assert np.max(np.abs(runs[0]["f"] - ref["f"])) < TOL[prec] * np.max(np.abs(ref["f"]))
 
 
 @pytest.mark.parametrize("force", ["sc", "zc", "hybrid"])

@@ -92,6 +92,15 @@ def test_invalid_parameters_rejected_without_device():
         assert st == 1 and lib.lbm_last_error(), bad
 
 
+def test_setters_reject_null_domain():
+    """The host-only tuning setters validate their handle without a device."""
+    lib = L.library()
+    assert lib.lbm_set_kernel(None, 0, 0) == 1
+    assert lib.lbm_set_chunks(None, 0) == 1
+    assert lib.lbm_set_access(None, 0) == 1
+    assert b"NULL" in lib.lbm_last_error()
+
+
 def test_largest_sides_accepted():
     """Sides up to 2^21 and nx ny up to 2^31 pass validation (the kernels'
     24-bit index arithmetic holds there)."""
