@@ -204,9 +204,9 @@ int64_t lbm_step_count(const lbm_domain* d);
  * The variant also picks how the reverse step (lbm_adjoint_step*) takes its y
  * derivatives where the HDM gradient has its geometric form along y (ny > 79;
  * Sec. 3.2, Eq. 20): by column marches under 3, from tiles under 1 and 2, and
- * under 0 by column marches once the lattice gives every compute unit two
- * 64-row column chunks (nxb * floor(ny / 64) >= 2 x compute units, nxb the
- * number of 64-column strips).  The results agree to rounding.
+ * under 0 by column marches once the lattice gives every compute unit 1.5
+ * 64-row column chunks (2 x nxb * floor(ny / 64) >= 3 x compute units, nxb
+ * the number of 64-column strips).  The results agree to rounding.
  * LBM_EINVAL for unknown values. */
 lbm_status lbm_set_kernel(lbm_domain* d, int32_t variant, int32_t tile_y);
 

@@ -556,26 +556,26 @@ lbm_status lbm_record(lbm_domain* d, int64_t nsteps, void* states, size_t stride
 }
 
 namespace {
-// Rows per tile of the reverse kernels: 16 where that still gives two tiles
-// per compute unit (a taller tile stages its +-R column halo for more rows),
-// else 8, or 4 when 8-row tiles would leave compute units idle (small
-// lattices).  The partials buffer is sized for 4.
-int adj_ty(const lbm_domain* d) {
-    if ((long)d->nxb * ((d->p.ny + 15) / 16) >= 2L * d->ncu) return 16;
-    return (long)d->nxb * ((d->p.ny + 7) / 8) >= d->ncu ? 8 : 4;
-}
+// Rows per tile of the reverse kernels.  Four-row tiles stage their whole
+// cross (or row bar) with every load in flight at once, three workgroups per
+// compute unit; they are the fastest measured at every size, on both paths
+// (reverse step, 16-row / 8-row / 4-row tiles: 384^2 42 / 38 / 26 us, 768^2
+// 100 / 90 / 74 us, 1280^2 243 / 252 / 191 us, 4096^2 with the column marches
+// 1.56 / 1.54 / 1.33 ms).
+constexpr int ADJ_TY = 4;
 // Chunks of the column march that takes the y derivatives of the reverse
 // step (k_adj_dy), or 0 where the tiles keep them.  The march needs the
 // geometric form along y (ny > 2R + 1, which also gives ny > (NB + 2) 8 + 3).
 // Kernel variant 3 (marching) always takes it there, variants 1 and 2 (tiles)
-// never; the automatic choice takes it once chunks of at least 64 rows give
-// every compute unit two wavefronts (at 1024^2, one per unit, the tiles are
-// faster: 0.135 against 0.146 ms).  About eight wavefronts per compute unit.
+// never; the automatic choice takes it once there are 1.5 64-row column
+// chunks per compute unit (tiles against column marches: 1024^2, 256 chunks,
+// 116 against 127 us; 1280^2, 400 chunks, 190 against 178 us).  About eight
+// wavefronts per compute unit.
 int adj_dy_chunks(const lbm_domain* d) {
     constexpr int R = lbm::Radius<double>::value;
     if (d->p.grad != LBM_GRAD_HDM || d->p.ny <= 2 * R + 1 || d->variant == 1 || d->variant == 2) return 0;
     const long most = std::max(1, d->p.ny / 64);
-    if (d->variant == 0 && (long)d->nxb * (d->p.ny / 64) < 2L * d->ncu) return 0;
+    if (d->variant == 0 && 2L * d->nxb * (d->p.ny / 64) < 3L * d->ncu) return 0;
     const long want = (8L * d->ncu + d->nxb - 1) / d->nxb;
     return (int)std::max(1L, std::min(most, want));
 }
@@ -590,7 +590,7 @@ AdjLayout adj_layout(const lbm_domain* d) {
     AdjLayout L;
     L.plane = align256((size_t)d->pitch * d->p.ny * sizeof(double));
     L.f = d->off_f[1];
-    const size_t nb = (size_t)d->nxb * ((d->p.ny + 3) / 4);
+    const size_t nb = (size_t)d->nxb * ((d->p.ny + ADJ_TY - 1) / ADJ_TY);
     L.part = align256(nb * 2 * sizeof(double));
     L.add = align256((size_t)d->p.nx * d->p.ny * sizeof(double));
     L.single = 4 * L.plane + L.part;
@@ -647,14 +647,13 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     A.e.c_att = d->p.k * d->p.a * d->alpha;
     A.e.c_attT = d->p.k * d->p.a * alpha_prime(d);
     A.e.kR = d->p.k * d->p.R;
-    const int ty = adj_ty(d);
-    dim3 grid(d->nxb, (d->p.ny + ty - 1) / ty);
+    const dim3 grid(d->nxb, (d->p.ny + ADJ_TY - 1) / ADJ_TY);
     const int nchunk = adj_dy_chunks(d);
     if (nchunk == 0 && (add_next || add_out))  // only the column-march passes take the factored form
         return fail(LBM_EINVAL, "factored cotangent without the column-march reverse step");
     const dim3 gdy((d->nxb + lbm::NT / lbm::BX - 1) / (lbm::NT / lbm::BX), nchunk > 0 ? nchunk : 1);
-    auto launch = [&](auto force, auto tyc) {
-        constexpr int F = decltype(force)::value, TY = decltype(tyc)::value;
+    auto launch = [&](auto force) {
+        constexpr int F = decltype(force)::value, TY = ADJ_TY;
         if (nchunk > 0) {  // y derivatives by column marches
             hipLaunchKernelGGL((lbm::k_adj_dy<F, 0>), gdy, dim3(lbm::NT), 0, stream, A, nchunk);
             if (add_next)
@@ -673,14 +672,10 @@ lbm_status adjoint_kernels(lbm_domain* d, const void* state_t, const double* lam
     };
     using SC = std::integral_constant<int, lbm::FORCE_SC>;
     using ZC = std::integral_constant<int, lbm::FORCE_ZC>;
-    using T4 = std::integral_constant<int, 4>;
-    using T8 = std::integral_constant<int, 8>;
-    using T16 = std::integral_constant<int, 16>;
-    if (d->p.force == LBM_FORCE_SC) {
-        if (ty == 16) launch(SC(), T16()); else if (ty == 8) launch(SC(), T8()); else launch(SC(), T4());
-    } else {
-        if (ty == 16) launch(ZC(), T16()); else if (ty == 8) launch(ZC(), T8()); else launch(ZC(), T4());
-    }
+    if (d->p.force == LBM_FORCE_SC)
+        launch(SC());
+    else
+        launch(ZC());
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
@@ -699,8 +694,7 @@ lbm_status adjoint_check(lbm_domain* d, const void* adj_ws, size_t adj_ws_bytes,
 
 lbm_status adjoint_reduce(lbm_domain* d, char* w, double* grad, hipStream_t stream) {
     AdjLayout L = adj_layout(d);
-    const int ty = adj_ty(d);
-    const long nb = (long)d->nxb * ((d->p.ny + ty - 1) / ty);
+    const long nb = (long)d->nxb * ((d->p.ny + ADJ_TY - 1) / ADJ_TY);
     hipLaunchKernelGGL(lbm::k_adj_accumulate, dim3(1), dim3(lbm::NT), 0, stream,
                        reinterpret_cast<const double*>(w + 4 * L.plane), nb, grad);
     HIP_TRY(hipGetLastError());
