@@ -305,6 +305,29 @@ def test_moments_match_oracle(prec, grad):
     assert abs(t[3] - vmax) < vb
 
 
+@pytest.mark.parametrize("variant,tile,chunks", [(2, 8, 0), (3, 8, 2)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_shift_equivariance(variant, tile, chunks, prec):
+    """The periodic step commutes with translations.  Shifting the initial
+    state by whole tiles or chunks (64 columns, 48 rows: two 48-row chunks of
+    the march, six 8-row tiles) shifts the result bitwise, since every cell's
+    arithmetic stays the same; any other shift moves the tile, chunk and
+    recursion-segment boundaries relative to the pattern and may change the
+    rounding only."""
+    po, rho0, ux0, uy0 = variant_case("cs", "sc", 128, 96, seed=17)
+    base = gpu_run(po, rho0, 30, prec, ux0, uy0, variant=variant, tile=tile, chunks=chunks)["f"]
+
+    def shifted(dy, dx):
+        def roll(a):
+            return np.roll(a, (dy, dx), axis=(0, 1))
+        f = gpu_run(po, roll(rho0), 30, prec, roll(ux0), roll(uy0), variant=variant, tile=tile, chunks=chunks)["f"]
+        return np.roll(f, (-dy, -dx), axis=(1, 2))
+
+    assert np.array_equal(shifted(48, 64), base)
+    odd = shifted(7, 13)
+    assert np.max(np.abs(odd - base)) <= TOL[prec] * np.max(np.abs(base))
+
+
 def test_x_invariance_bitwise():
     """A noise-free y-slab stays bitwise x-invariant on the GPU (fused kernel,
     two x-blocks)."""
