@@ -443,6 +443,40 @@ def surface_tension_report(slab_steps: int = 40000, drop_steps: int = 20000):
     return out
 
 
+def spurious_report(steps: int = 20000, n: int = 200, radius: float = 30.0):
+    """Sec. 5.4, Fig. 7: spurious currents of a droplet at rest (radius 30 on
+    200^2, W = 4, Shan-Chen force, Eq. 20, tau = 1) for the four EOS of the
+    coexistence study with their k, at T_r = 0.5 .. 0.9, one batched run: the
+    largest velocity (|v| of Eq. 11 over the lattice, which peaks at the
+    interface) after `steps` steps, None where the run went non-finite."""
+    import paper_1712_06079_amd as L
+    import torch
+    trs = (0.5, 0.6, 0.7, 0.8, 0.9)
+    ps, rhos, lab = [], [], []
+    for eos, c in FIG5_EOS.items():
+        for tr in trs:
+            p = L.Params(nx=n, ny=n, eos=eos, force="sc", R=1.0, tau=1.0, **c)
+            tc, _ = L.critical(p)
+            p.T = tr * tc
+            rv, rl, _ = L.maxwell(p, p.T)
+            ps.append(p)
+            rhos.append(torch.from_numpy(I.droplet(n, n, rv, rl, radius, 4.0)).cuda())
+            lab.append((eos, tr))
+    b = L.Batch(ps, rhos)
+    b.step(steps)
+    bad = b.check_finite()
+    out = {"steps": steps, "lattice": [n, n], "radius": radius, "tau": 1.0, "per_eos": {}}
+    for i, (eos, tr) in enumerate(lab):
+        v = None if bad[i] else float(b.domain(i).moments(want=("rho",))["totals"][3].item())
+        out["per_eos"].setdefault(eos, []).append({"T_r": tr, "max_v": v})
+    vals = [r["max_v"] for rows in out["per_eos"].values() for r in rows if r["max_v"] is not None]
+    out["max_v"] = max(vals) if vals else None
+    out["nonfinite"] = int(sum(bad))
+    print(f"[bench] spurious currents: max |v| {out['max_v']}, {out['nonfinite']} non-finite",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def splash_report(re_list=(40.0, 100.0, 173.0), U: float = 0.05, R: float = 108.0, t_star_end: float = 1.5,
                   every: int = 50, tau_floor: float = 0.824):
     """Sec. 5.5: a droplet splashing on a thin liquid film.  PR water (a = 9/49,
@@ -1035,6 +1069,7 @@ def main():
                     help="lattice sides of the per-step reverse-sweep cost curve (none = skip)")
     ap.add_argument("--fig5-steps", type=int, default=60000, help="steps of the coexistence comparison (0 = skip)")
     ap.add_argument("--no-sigma", dest="sigma", action="store_false", help="skip the surface-tension report")
+    ap.add_argument("--spurious-steps", type=int, default=20000, help="steps of the spurious-current report (0 = skip)")
     ap.add_argument("--splash-re", type=float, nargs="*", default=[40.0, 100.0, 173.0],
                     help="Reynolds numbers of the droplet-splash runs (none = skip)")
     ap.add_argument("--droplet-steps", type=int, default=20000, help="single-droplet (1024^2) steps (0 = skip)")
@@ -1088,6 +1123,7 @@ def main():
               f"{batch['domain_steps_per_s_separate']:.0f} separate", file=sys.stderr, flush=True)
     fig5 = fig5_coexistence(args.fig5_steps) if args.fig5_steps > 0 else None
     sigma = surface_tension_report() if args.sigma else None
+    spurious = spurious_report(args.spurious_steps) if args.spurious_steps > 0 else None
     splash = splash_report(tuple(args.splash_re)) if args.splash_re else None
     adjoint = None
     if args.adjoint_steps > 0:
@@ -1132,6 +1168,8 @@ def main():
         line["fig5_coexistence"] = fig5
     if sigma:
         line["surface_tension"] = sigma
+    if spurious:
+        line["spurious_velocity"] = spurious
     if splash:
         line["splash"] = splash
     if adjoint:

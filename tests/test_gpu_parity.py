@@ -551,6 +551,34 @@ def test_laplace_law(tr):
     assert np.max(np.abs(dp / inv / table[tr] - 1)) < 0.04
 
 
+def test_spurious_currents():
+    """Sec. 5.4, Fig. 7: a droplet of radius 30 at rest on 200^2 (SC, Eq. 20,
+    tau = 1, the paper's k per EOS) for the van der Waals, Peng-Robinson (with
+    its alpha(T)), Carnahan-Starling and Redlich-Kwong EOS at T_r = 0.6 .. 0.9,
+    20 000 batched steps: the largest velocity stays well below 0.1 and grows
+    as the temperature falls."""
+    trs = (0.6, 0.7, 0.8, 0.9)
+    kinds = ("vdw", "pr", "cs", "rk")
+    ps, rhos = [], []
+    for kind in kinds:
+        for tr in trs:
+            po = PINS.eos_params(kind)
+            po.nx = po.ny = 200
+            tc, _ = O.critical(po)
+            po.T = tr * tc
+            rv, rl, _ = O.maxwell(po, po.T)
+            ps.append(lib_params(po))
+            rhos.append(dev(I.droplet(200, 200, rv, rl, 30.0, 4.0)))
+    b = L.Batch(ps, rhos)
+    b.step(20000)
+    assert not any(b.check_finite())
+    vmax = np.array([float(b.domain(i).moments(want=("rho",))["totals"][3]) for i in range(len(ps))])
+    vmax = vmax.reshape(len(kinds), len(trs))
+    print(dict(zip(kinds, vmax.tolist())))
+    assert vmax.max() < 0.1
+    assert np.all(np.diff(vmax, axis=1) < 0)
+
+
 def wall_case(eos, force, nx, ny, seed):
     """A droplet resting near the lower wall of a channel (walls at y = -1/2 and
     ny - 1/2), with velocity noise."""
