@@ -443,6 +443,67 @@ def surface_tension_report(slab_steps: int = 40000, drop_steps: int = 20000):
     return out
 
 
+def laplace_fig6(steps: int = 20000, radii=(16.0, 24.0, 32.0, 40.0)):
+    """Sec. 5.3, Fig. 6: pressure jump against inverse radius for the van der
+    Waals fluid (a = 9/49, b = 2/21, k = 0.01, tau = 1, SC + Eq. 20), droplets
+    of radius 16 .. 40 on 128^2 at T_r = 0.4 .. 0.8, one batched run: per
+    droplet the equimolar radius R_e and dp = p_in - p_out (p = rho/3 + U);
+    per temperature the least-squares line dp = sigma / R_e + c beside Table
+    1's sigma_L.  A droplet that evaporated (its centre below the mean of the
+    two phases), is still evaporating (R_e below 0.8 of its initial radius:
+    radius 16 at T_r = 0.8) or went non-finite is reported and left out of
+    the fit."""
+    import paper_1712_06079_amd as L
+    import torch
+    trs = (0.4, 0.5, 0.6, 0.7, 0.8)
+    tc = 8 * (9 / 49) / (27 * (2 / 21))
+    ps, rhos, lab = [], [], []
+    for tr in trs:
+        p = L.Params(nx=128, ny=128, eos="vdw", force="sc", a=9 / 49, b=2 / 21, R=1.0, k=0.01, tau=1.0, T=tr * tc)
+        rv, rl, _ = L.maxwell(p, p.T)
+        for r in radii:
+            ps.append(p)
+            rhos.append(torch.from_numpy(I.droplet(128, 128, rv, rl, r, 4.0)).cuda())
+            lab.append((tr, r, rv, rl))
+    b = L.Batch(ps, rhos)
+    b.step(steps)
+    bad = b.check_finite()
+    out = {"steps": steps, "lattice": [128, 128], "radii": list(radii), "per_T_r": []}
+    for tr in trs:
+        pts = []
+        for i, (t, r, rv, rl) in enumerate(lab):
+            if t != tr:
+                continue
+            row = {"R0": r}
+            if bad[i]:
+                row["state"] = "non-finite"
+            else:
+                m = b.domain(i).moments(want=("rho", "p"))
+                rho, pr = m["rho"].cpu().numpy(), m["p"].cpu().numpy()
+                ri, ro = rho[64, 64], rho[0, 0]
+                if ri < 0.5 * (rv + rl):
+                    row["state"] = "evaporated"
+                else:
+                    re = float(np.sqrt(((rho - ro) / (ri - ro)).sum() / np.pi))
+                    dp = float(pr[64, 64] - pr[0, 0])
+                    row.update({"state": "droplet" if re >= 0.8 * r else "shrinking", "R_e": re, "dp": dp,
+                                "dp_R_e": dp * re})
+            pts.append(row)
+        rec = {"T_r": tr, "droplets": pts, "paper_sigma_L": TABLE1.get(tr, (None, None))[1]}
+        ok = [q for q in pts if q["state"] == "droplet"]
+        if len(ok) >= 2:
+            inv = np.array([1.0 / q["R_e"] for q in ok])
+            dp = np.array([q["dp"] for q in ok])
+            A = np.vstack([inv, np.ones_like(inv)]).T
+            (sig, c), *_ = np.linalg.lstsq(A, dp, rcond=None)
+            rec.update({"sigma_fit": float(sig), "intercept": float(c),
+                        "max_rel_residual": float(np.max(np.abs(A @ np.array([sig, c]) - dp) / np.abs(dp)))})
+        out["per_T_r"].append(rec)
+    print("[bench] Fig. 6: " + ", ".join(f"T_r {r['T_r']} sigma {r.get('sigma_fit', float('nan')):.4f}"
+                                         for r in out["per_T_r"]), file=sys.stderr, flush=True)
+    return out
+
+
 def spurious_report(steps: int = 20000, n: int = 200, radius: float = 30.0):
     """Sec. 5.4, Fig. 7: spurious currents of a droplet at rest (radius 30 on
     200^2, W = 4, Shan-Chen force, Eq. 20, tau = 1) for the four EOS of the
@@ -1123,6 +1184,7 @@ def main():
               f"{batch['domain_steps_per_s_separate']:.0f} separate", file=sys.stderr, flush=True)
     fig5 = fig5_coexistence(args.fig5_steps) if args.fig5_steps > 0 else None
     sigma = surface_tension_report() if args.sigma else None
+    fig6 = laplace_fig6() if args.sigma else None
     spurious = spurious_report(args.spurious_steps) if args.spurious_steps > 0 else None
     splash = splash_report(tuple(args.splash_re)) if args.splash_re else None
     adjoint = None
@@ -1168,6 +1230,8 @@ def main():
         line["fig5_coexistence"] = fig5
     if sigma:
         line["surface_tension"] = sigma
+    if fig6:
+        line["laplace_fig6"] = fig6
     if spurious:
         line["spurious_velocity"] = spurious
     if splash:
