@@ -139,7 +139,8 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
     }
     int& per_cu = ty == 4 ? d->march_occ[0] : d->march_occ[1];  // cached occupancy query
     if (per_cu == 0) {
-        // the instantiation launch_march_t picks for this N_x (paired accesses when even)
+        // the instantiation launch_march_t picks for this N_x (paired accesses when
+        // even; the plain-access twin has the same registers and LDS)
         const bool vec = d->p.nx % 2 == 0;
         const auto occ = [&](const void* kern) {
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, lbm::NT, 0);
