@@ -165,15 +165,53 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
 // buffers or snapshot slots, with the selected kernel.
 // Automatic choice (variant 0): the marching kernel when its chunks keep at
 // least 16 rows each (shorter chunks spend most of their time in the chunk
-// prologue), otherwise tiles, halved in height until there are at least as
-// many tiles as compute units.
+// prologue), otherwise tiles (auto_tile).
 constexpr int MARCH_MIN_ROWS = 16;
 
-template <typename Real>
-int auto_tile(const lbm_domain* d) {
+// Resident tile-kernel workgroups per CU at tile height ty (cached per domain).
+template <typename Real, int FORCE>
+lbm_status fused_occupancy(lbm_domain* d, int ty, int* per_cu) {
+    int& n = d->fused_occ[ty == 4 ? 0 : (ty == 8 ? 1 : 2)];
+    if (n == 0) {
+        const bool g9 = d->p.grad == LBM_GRAD_CDM9;
+        auto occ = [&](const void* kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, lbm::NT, 0); };
+        if (ty == 4)
+            HIP_TRY(g9 ? occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 4, 4, true>)
+                       : occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 4, 4>));
+        else if (ty == 8)
+            HIP_TRY(g9 ? occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 8, 4, true>)
+                       : occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 8, 4>));
+        else
+            HIP_TRY(g9 ? occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 16, 4, true>)
+                       : occ((const void*)lbm::k_fused<Real, FORCE, lbm::BX, 16, 4>));
+        if (n < 1) n = 1;
+    }
+    *per_cu = n;
+    return LBM_OK;
+}
+
+// Tile height: the smallest (most tiles) whose tiles all fit one set of
+// resident workgroups; a few tiles over it would run as a second round
+// (FP32 512^2: 8-row tiles, 512 in 512 slots, 12.7 us per step, against 15.0
+// for 16-row tiles; 640^2: 16-row tiles, 400 in 512, 19.1 against 20.9 for
+// 8-row ones, 1600 > 768).  Where no height fits one round, the default (8
+// rows FP64, 16 FP32) halved until there are at least as many tiles as
+// compute units.
+template <typename Real, int FORCE>
+lbm_status auto_tile(lbm_domain* d, int* ty_out) {
+    for (int ty = 4; ty <= 16; ty *= 2) {
+        int per_cu = 1;
+        const lbm_status st = fused_occupancy<Real, FORCE>(d, ty, &per_cu);
+        if (st != LBM_OK) return st;
+        if ((long)d->nxb * ((d->p.ny + ty - 1) / ty) <= (long)d->ncu * per_cu) {
+            *ty_out = ty;
+            return LBM_OK;
+        }
+    }
     int ty = sizeof(Real) == 8 ? 8 : 16;
     while (ty > 4 && (long)d->nxb * ((d->p.ny + ty - 1) / ty) < d->ncu) ty /= 2;
-    return ty;
+    *ty_out = ty;
+    return LBM_OK;
 }
 
 // Capacity of the last-level (Infinity) cache of gfx950 in bytes.  A state
@@ -222,8 +260,11 @@ lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f
             st = march_chunks<Real, F>(d, ty, &nchunk);
             if (st == LBM_OK && !lbm::launch_march<Real, F>(a, ty, nchunk, march_cached(d), s))
                 st = fail(LBM_EUNSUPPORTED, "marching kernel: unsupported block height %d", ty);
-        } else if (!lbm::launch_fused<Real, F>(a, d->variant == 0 ? auto_tile<Real>(d) : d->tile_y, s)) {
-            st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", d->tile_y);
+        } else {
+            int ty = d->tile_y;
+            if (d->variant == 0) st = auto_tile<Real, F>(d, &ty);
+            if (st == LBM_OK && !lbm::launch_fused<Real, F>(a, ty, s))
+                st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", ty);
         }
     });
     if (st != LBM_OK) return st;

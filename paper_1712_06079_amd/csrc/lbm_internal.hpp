@@ -27,6 +27,7 @@ struct lbm_domain {
     int access;        // marching kernel's population accesses: 0 automatic, 1 non-temporal, 2 plain
     int ncu;           // compute units of the device
     int march_occ[2];  // resident marching workgroups per CU (block rows 4, 8; 0 = not queried)
+    int fused_occ[3];  // resident tile-kernel workgroups per CU (tile rows 4, 8, 16; 0 = not queried)
     char* ws;
     size_t ws_bytes;
     size_t off_f[2], off_phi[2], off_part, off_scr, off_tab;
