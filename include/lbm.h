@@ -192,8 +192,8 @@ int64_t lbm_step_count(const lbm_domain* d);
  *   0  fused single pass, chosen automatically (the default): the strip-
  *      marching kernel when the HDM gradient takes its geometric form along y
  *      (grad = HDM and ny > 2R + 1, R = 39 for FP64 and 28 for FP32
- *      populations) and its automatic chunks keep >= 16 rows each (large
- *      lattices), otherwise independent tiles of the smallest height (4, 8
+ *      populations) and its automatic chunks keep >= 16 rows each (11 with
+ *      FP32 populations; large lattices), otherwise independent tiles of the smallest height (4, 8
  *      or 16 rows) whose tiles all fit one set of resident workgroups, or
  *      where none does, of a height that gives at least one tile per
  *      compute unit;

@@ -164,9 +164,13 @@ lbm_status march_chunks(lbm_domain* d, int ty, int* nchunk) {
 // One step from (f_in, phi_in) to (f_out, phi_out), any of the domain's
 // buffers or snapshot slots, with the selected kernel.
 // Automatic choice (variant 0): the marching kernel when its chunks keep at
-// least 16 rows each (shorter chunks spend most of their time in the chunk
-// prologue), otherwise tiles (auto_tile).
-constexpr int MARCH_MIN_ROWS = 16;
+// least 16 rows each with FP64 populations, 11 with FP32 (shorter chunks
+// spend most of their time in the chunk prologue, about R + NB TY potential
+// rows: 79 FP64, 60 FP32), otherwise tiles (auto_tile).  FP32 736^2 to 832^2
+// (11.5 - 14.1 rows per chunk): march 22.0 - 25.6 us per step against 26.9 -
+// 29.1 for the best tiles; FP32 704^2 (10.2 rows): tiles 19.8 against 21.6.
+template <typename Real>
+constexpr int march_min_rows() { return sizeof(Real) == 8 ? 16 : 11; }
 
 // Resident tile-kernel workgroups per CU at tile height ty (cached per domain).
 template <typename Real, int FORCE>
@@ -240,7 +244,7 @@ lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f
         if (d->variant == 0 && march_eligible(d)) {
             int nchunk = 1;
             st = march_chunks<Real, F>(d, march_rows(d), &nchunk);
-            march = st == LBM_OK && d->p.ny / nchunk >= MARCH_MIN_ROWS;
+            march = st == LBM_OK && d->p.ny / nchunk >= march_min_rows<Real>();
         }
         if (st != LBM_OK) return;
         auto a = make_args<Real>(d, d->cur, 1 - d->cur);
