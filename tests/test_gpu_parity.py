@@ -328,6 +328,29 @@ def test_shift_equivariance(variant, tile, chunks, prec):
     assert np.max(np.abs(odd - base)) <= TOL[prec] * np.max(np.abs(base))
 
 
+@pytest.mark.parametrize("variant,tile", [(2, 8), (3, 8)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mirror_equivariance(variant, tile, prec):
+    """Reflecting the initial state in x (or y), with the velocity component
+    along that axis reversed, reflects the result, with e_x (or e_y) reversed
+    in the population index: to the parity tolerance, not bitwise, since the
+    recursions of Eq. 20 then run the other way along each line."""
+    po, rho0, ux0, uy0 = variant_case("cs", "sc", 128, 96, seed=23)
+    base = gpu_run(po, rho0, 30, prec, ux0, uy0, variant=variant, tile=tile, chunks=2)["f"]
+    scale = np.max(np.abs(base))
+    for axis in ("x", "y"):
+        sx, sy = (-1, 1) if axis == "x" else (1, -1)
+        perm = [int(np.nonzero((O.EX == sx * O.EX[i]) & (O.EY == sy * O.EY[i]))[0][0]) for i in range(9)]
+
+        def flip(a):
+            return np.ascontiguousarray(a[:, ::-1] if axis == "x" else a[::-1, :])
+
+        f = gpu_run(po, flip(rho0), 30, prec, sx * flip(ux0), sy * flip(uy0), variant=variant, tile=tile,
+                    chunks=2)["f"]
+        back = f[perm][:, :, ::-1] if axis == "x" else f[perm][:, ::-1, :]
+        assert np.max(np.abs(back - base)) <= TOL[prec] * scale, axis
+
+
 def test_x_invariance_bitwise():
     """A noise-free y-slab stays bitwise x-invariant on the GPU (fused kernel,
     two x-blocks)."""
