@@ -227,6 +227,16 @@ lbm_status lbm_set_chunks(lbm_domain* d, int32_t nchunk);
  * non-temporal accesses.  LBM_EINVAL for other values. */
 lbm_status lbm_set_access(lbm_domain* d, int32_t access);
 
+/* What lbm_step launches for this domain under its current settings (host;
+ * for tuning and tests; the first call per tile or block height queries the
+ * device's occupancy): *kernel 1 (two-pass reference), 2 (tiles) or 3 (strip
+ * march); *rows the tile height or the march's rows per block; *chunks the
+ * march's y chunks per 64-column strip (0 for the other kernels); *cached 1
+ * when the march uses plain (cached) population accesses, else 0.
+ * LBM_EUNSUPPORTED where lbm_step would fail the same way (variant 3 on a
+ * domain it cannot march, variant 1 with walls); LBM_EINVAL for NULL. */
+lbm_status lbm_kernel_choice(lbm_domain* d, int32_t* kernel, int32_t* rows, int32_t* chunks, int32_t* cached);
+
 /* Check the current density (Eq. 3) for non-finite values (synchronises
  * `stream`): *ok = 1 if every rho is finite, else 0 (and the call returns
  * LBM_ENONFINITE).  A non-finite density is how a run that has left the

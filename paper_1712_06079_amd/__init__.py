@@ -87,6 +87,7 @@ def library():
         L.lbm_set_kernel.argtypes = [_VP, C.c_int32, C.c_int32]
         L.lbm_set_chunks.argtypes = [_VP, C.c_int32]
         L.lbm_set_access.argtypes = [_VP, C.c_int32]
+        L.lbm_kernel_choice.argtypes = [_VP] + [C.POINTER(C.c_int32)] * 4
         L.lbm_check_finite.argtypes = [_VP, C.POINTER(C.c_int32), _VP]
         L.lbm_state_bytes.argtypes = [_VP, C.POINTER(C.c_size_t)]
         L.lbm_save_state.argtypes = [_VP, _VP, _VP]
@@ -107,7 +108,7 @@ def library():
         L.lbm_destroy.restype = None
         L.lbm_last_error.restype = C.c_char_p
         for fn in ("lbm_critical", "lbm_maxwell", "lbm_workspace_bytes", "lbm_hdm_row", "lbm_init", "lbm_step", "lbm_moments",
-                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_set_access", "lbm_check_finite",
+                   "lbm_get_populations", "lbm_set_populations", "lbm_set_kernel", "lbm_set_chunks", "lbm_set_access", "lbm_kernel_choice", "lbm_check_finite",
                    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_adjoint_workspace_bytes",
                    "lbm_adjoint_step", "lbm_adjoint_rho0", "lbm_record", "lbm_adjoint_steps", "lbm_stream_probe",
                    "lbm_adjoint_step_noalloc", "lbm_interface_excess", "lbm_flat_profile", "lbm_sigma_slab"):
@@ -252,6 +253,14 @@ class Domain:
         """Marching kernel's population accesses: 0 automatic (plain when the
         state fits in the last-level cache), 1 non-temporal, 2 plain."""
         check(library().lbm_set_access(self._h, access))
+
+    def kernel_choice(self) -> dict:
+        """What step() launches: kernel 1 (two-pass reference), 2 (tiles) or
+        3 (strip march), rows (tile height or block rows), chunks (the march's
+        y chunks per strip) and cached (plain population accesses)."""
+        v = [C.c_int32() for _ in range(4)]
+        check(library().lbm_kernel_choice(self._h, *[C.byref(x) for x in v]))
+        return dict(zip(("kernel", "rows", "chunks", "cached"), (x.value for x in v)))
 
     def step(self, n: int = 1, stream=None):
         check(library().lbm_step(self._h, int(n), _stream(stream)))

@@ -232,43 +232,69 @@ bool march_cached(const lbm_domain* d) {
     return state <= LLC_BYTES;
 }
 
-lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f_out, void* phi_out, hipStream_t s) {
+// What one step launches: kernel 1 (two-pass reference), 2 (tiles) or 3
+// (strip march), the tile height or marching block rows, the march's y chunks
+// per strip and whether it uses plain (cached) population accesses.
+struct KernelChoice {
+    int kernel, rows, chunks, cached;
+};
+
+template <typename Real, int F>
+lbm_status choose_kernel(lbm_domain* d, KernelChoice* c) {
     if (d->variant == 3 && !march_eligible(d))
         return fail(LBM_EUNSUPPORTED, "marching kernel needs the HDM gradient, a periodic and longer y axis (ny = %d)", d->p.ny);
     if (d->variant == 1 && d->p.walls) return fail(LBM_EUNSUPPORTED, "the two-pass reference kernel has no walls");
+    c->chunks = 0;
+    c->cached = 0;
+    if (d->variant == 1) {
+        c->kernel = 1;
+        c->rows = d->tile_y <= 8 ? 8 : 16;
+        return LBM_OK;
+    }
+    bool march = d->variant == 3;
+    int nchunk = 0;
+    if (march || (d->variant == 0 && march_eligible(d))) {
+        const lbm_status st = march_chunks<Real, F>(d, march_rows(d), &nchunk);
+        if (st != LBM_OK) return st;
+        if (!march) march = d->p.ny / nchunk >= march_min_rows<Real>();
+    }
+    if (march) {
+        c->kernel = 3;
+        c->rows = march_rows(d);
+        c->chunks = nchunk;
+        c->cached = march_cached(d) && d->p.nx % 2 == 0;  // odd N_x: non-temporal always
+        return LBM_OK;
+    }
+    c->kernel = 2;
+    if (d->variant == 0) return auto_tile<Real, F>(d, &c->rows);
+    c->rows = d->tile_y ? d->tile_y : (sizeof(Real) == 8 ? 8 : 16);
+    return LBM_OK;
+}
+
+lbm_status run_step(lbm_domain* d, const void* f_in, const void* phi_in, void* f_out, void* phi_out, hipStream_t s) {
     lbm_status st = LBM_OK;
     dispatch(d, [&](auto real, auto force) {
         using Real = decltype(real);
         constexpr int F = decltype(force)::value;
-        bool march = d->variant == 3;
-        if (d->variant == 0 && march_eligible(d)) {
-            int nchunk = 1;
-            st = march_chunks<Real, F>(d, march_rows(d), &nchunk);
-            march = st == LBM_OK && d->p.ny / nchunk >= march_min_rows<Real>();
-        }
+        KernelChoice c;
+        st = choose_kernel<Real, F>(d, &c);
         if (st != LBM_OK) return;
         auto a = make_args<Real>(d, d->cur, 1 - d->cur);
         a.f_in = static_cast<const Real*>(f_in);
         a.phi_in = phi_in;
         a.f_out = static_cast<Real*>(f_out);
         a.phi_out = phi_out;
-        if (d->variant == 1) {
-            if (d->tile_y <= 8) launch_ref<Real, F, 8>(d, a, s);
+        if (c.kernel == 1) {
+            if (c.rows == 8) launch_ref<Real, F, 8>(d, a, s);
             else launch_ref<Real, F, 16>(d, a, s);
             auto b = a;  // potential field of the new state
             b.f_in = a.f_out;
             hipLaunchKernelGGL((lbm::k_phi<Real, F>), dim3(grid_1d((long)d->pitch * d->p.ny)), dim3(lbm::NT), 0, s, b);
-        } else if (march) {
-            const int ty = march_rows(d);
-            int nchunk = 1;
-            st = march_chunks<Real, F>(d, ty, &nchunk);
-            if (st == LBM_OK && !lbm::launch_march<Real, F>(a, ty, nchunk, march_cached(d), s))
-                st = fail(LBM_EUNSUPPORTED, "marching kernel: unsupported block height %d", ty);
-        } else {
-            int ty = d->tile_y;
-            if (d->variant == 0) st = auto_tile<Real, F>(d, &ty);
-            if (st == LBM_OK && !lbm::launch_fused<Real, F>(a, ty, s))
-                st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", ty);
+        } else if (c.kernel == 3) {
+            if (!lbm::launch_march<Real, F>(a, c.rows, c.chunks, c.cached != 0, s))
+                st = fail(LBM_EUNSUPPORTED, "marching kernel: unsupported block height %d", c.rows);
+        } else if (!lbm::launch_fused<Real, F>(a, c.rows, s)) {
+            st = fail(LBM_EUNSUPPORTED, "fused kernel: unsupported tile height %d", c.rows);
         }
     });
     if (st != LBM_OK) return st;
@@ -539,6 +565,21 @@ lbm_status lbm_set_access(lbm_domain* d, int32_t access) {
     if (!d) return fail(LBM_EINVAL, "NULL domain");
     if (access < 0 || access > 2) return fail(LBM_EINVAL, "access mode %d not in 0 .. 2", access);
     d->access = access;
+    return LBM_OK;
+}
+
+lbm_status lbm_kernel_choice(lbm_domain* d, int32_t* kernel, int32_t* rows, int32_t* chunks, int32_t* cached) {
+    if (!d || !kernel || !rows || !chunks || !cached) return fail(LBM_EINVAL, "NULL argument");
+    lbm_status st = LBM_OK;
+    KernelChoice c{};
+    dispatch(d, [&](auto real, auto force) {
+        st = choose_kernel<decltype(real), decltype(force)::value>(d, &c);
+    });
+    if (st != LBM_OK) return st;
+    *kernel = c.kernel;
+    *rows = c.rows;
+    *chunks = c.chunks;
+    *cached = c.cached;
     return LBM_OK;
 }
 

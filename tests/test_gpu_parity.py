@@ -371,6 +371,48 @@ def test_mass_momentum_conservation(force, variant, tile):
     assert abs(m[1]) < 1e-12 * m0[0] and abs(m[2]) < 1e-12 * m0[0]
 
 
+def test_kernel_choice():
+    """The automatic decisions of lbm_step, read back: the march's chunk count
+    is the most whose workgroups are all resident at once (two per CU with
+    FP64 populations: 1152^2 has 18 strips), plain population accesses where
+    the state fits the 256 MiB last-level cache (or as set; never on odd
+    N_x), tiles whose count fits one set of resident workgroups (FP32 512^2:
+    8 rows), the FP32 march from 11 rows per chunk (736^2), 4-row tiles on
+    small lattices."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def domain(ny, prec, nx=None):
+        nx = nx or ny
+        p = L.Params(nx=nx, ny=ny, eos="cs", force="sc", a=1.0, b=4.0, R=1.0, k=0.04, tau=1.0, prec=prec)
+        p.T = 0.5 * L.critical(p)[0]
+        return L.Domain(p, torch.full((ny, nx), 0.1, dtype=torch.float64, device="cuda"))
+
+    d = domain(1152, "f64")
+    c = d.kernel_choice()
+    assert c["kernel"] == 3 and c["rows"] == 8 and c["cached"] == 1
+    assert 18 * c["chunks"] <= 2 * ncu < 18 * (c["chunks"] + 1)
+    d.set_access(1)
+    assert d.kernel_choice()["cached"] == 0
+    del d
+    d = domain(1448, "f64")  # 320 MiB of state
+    assert d.kernel_choice()["cached"] == 0
+    d.set_access(2)
+    assert d.kernel_choice()["cached"] == 1
+    del d
+    assert domain(1024, "f64", nx=1023).kernel_choice()["cached"] == 0
+    assert domain(512, "f32").kernel_choice() == {"kernel": 2, "rows": 8, "chunks": 0, "cached": 0}
+    assert domain(704, "f32").kernel_choice()["kernel"] == 2
+    assert domain(736, "f32").kernel_choice()["kernel"] == 3
+    assert domain(256, "f64").kernel_choice() == {"kernel": 2, "rows": 4, "chunks": 0, "cached": 0}
+    d = domain(60, "f64", nx=64)
+    d.set_kernel(2, 16)
+    assert d.kernel_choice()["rows"] == 16
+    d.set_kernel(3, 8)
+    with pytest.raises(L.LBMError) as e:
+        d.kernel_choice()
+    assert e.value.status == 5
+
+
 def test_x_invariance_bitwise():
     """A noise-free y-slab stays bitwise x-invariant on the GPU (fused kernel,
     two x-blocks)."""

@@ -98,6 +98,8 @@ def test_setters_reject_null_domain():
     assert lib.lbm_set_kernel(None, 0, 0) == 1
     assert lib.lbm_set_chunks(None, 0) == 1
     assert lib.lbm_set_access(None, 0) == 1
+    v = C.c_int32()
+    assert lib.lbm_kernel_choice(None, C.byref(v), C.byref(v), C.byref(v), C.byref(v)) == 1
     assert b"NULL" in lib.lbm_last_error()
 
 
