@@ -135,7 +135,7 @@ def run_gpu(name: str, prec: str, steps: int, warmup: int, variant: int = 0, til
     return {
         "desc": desc, "params": p, "mlups": mlups, "ms_per_step": ms_total / steps, "wall_s": wall,
         "launch_ms_mean": launch_ms, "achieved_gbs": achieved, "alg_bytes_per_launch": alg_bytes, "finite": ok,
-        "domain": d, "device_warmup_s": round(warm, 2),
+        "domain": d, "device_warmup_s": round(warm, 2), "launch": d.kernel_choice(),
     }
 
 
@@ -1215,7 +1215,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": r["desc"], "storage": args.prec, "nx": p.nx, "ny": p.ny, "eos": p.eos, "force": p.force, "grad": p.grad,
                    "tau": p.tau, "k": p.k, "T": p.T, "seed": 2024, "kernel": kname,
-                   "finite": r["finite"]},
+                   "finite": r["finite"], "launch": r["launch"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
