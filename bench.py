@@ -893,13 +893,14 @@ def droplet_report(steps: int):
         out[prec] = {"steps": steps, "mlups": round(mlups, 1),
                      "roofline_frac": round(mlups * 1e6 * 2 * Q * es / (HBM_PEAK_GBS * 1e9), 4),
                      "max_v": float(m["totals"][3]), "dp": dp, "R_eff": round(reff, 3), "sigma_L": dp * reff,
-                     "mass": float(m["totals"][0]), "finite": d.check_finite()}
+                     "mass": float(m["totals"][0]), "finite": d.check_finite(), "launch": d.kernel_choice()}
         rhos[prec] = rho
         print(f"[bench] c2 {prec}: {mlups:.0f} MLUPS, max|v| {out[prec]['max_v']:.3e}, dp {dp:.4e}, "
               f"R_eff {reff:.2f}, sigma_L {dp * reff:.4e}", file=sys.stderr, flush=True)
         del d
     out["f32_vs_f64"] = _precision_diff(rhos, out["f64"], out["f32"], ("dp", "sigma_L", "max_v"))
-    out["note"] = "1024^2: 168 MB of FP64 state, resident in the 256 MB Infinity Cache (not an HBM roofline case)"
+    out["note"] = ("1024^2: 168 MB of FP64 state, resident in the 256 MB Infinity Cache (not an HBM roofline case; "
+                   "the strip march reads and writes it with plain, cached accesses: launch.cached)")
     out["desc"] = desc
     return out
 
